@@ -1,0 +1,167 @@
+/*
+ * cgks.h -- C ABI of the MI355X (gfx950) CGKS-5th / GKS-2nd stage sweep library, libcgks.so.
+ *
+ * Method: Yang, Zhao, Xu, "Performance evaluation of high-order compact and second-order
+ * gas-kinetic schemes in compressible flow simulations", arXiv 2508.19911.  The library advances the
+ * compressible Navier-Stokes equations (through the BGK model, Sec. 2) on a uniform, structured,
+ * triply periodic box with either
+ *   - CGKS-5th (Sec. 3.2): compact P^4 reconstruction from cell averages and cell-averaged
+ *     gradients on the 19-cell stencil, optional GENO blend (eq. weno-new), gas-kinetic flux at the
+ *     2x2 Gauss points of every face (eq. flux, deri-t-f, deri-t-q), two-stage fourth-order update
+ *     of the averages and of the gradients (Sec. 3.4); or
+ *   - GKS-2nd (Sec. 3.3): P^1 with an optional Venkatakrishnan limiter, the same flux at the face
+ *     midpoints, Q^{n+1} = Q^n + dt L + dt^2/2 dL/dt (Sec. 3.4).
+ * The time step follows the CFL and viscous conditions of Sec. 4 (opening).
+ *
+ * Conventions
+ *   - Every call returns int: CGKS_OK (0) or a negative error code; cgks_strerror() gives text.
+ *   - Fields are SoA, x fastest: q[v][nz][ny][nx], v = (rho, rho U, rho V, rho W, rho E);
+ *     gradients g[15][...] = d/dx of the 5 variables, then d/dy, then d/dz.
+ *   - Host arrays are owned by the caller; copies are complete when the call returns.
+ *   - The device workspace (cgks_workspace_bytes) and the HIP stream are owned by the caller (for
+ *     example a torch uint8 tensor and torch.cuda.current_stream()); the library allocates no device
+ *     memory and launches every kernel on that stream.  The workspace must be 256-byte aligned and
+ *     outlive the context.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef CGKS_H
+#define CGKS_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CGKS_OK = 0,
+  CGKS_EINVAL = -1,        /* bad size, parameter or enum */
+  CGKS_EWORKSPACE = -2,    /* workspace missing, too small or misaligned */
+  CGKS_EDEVICE = -3,       /* a HIP call failed (message kept for cgks_strerror) */
+  CGKS_ENONPHYSICAL = -4,  /* rho <= 0, p <= 0 or NaN found at the start of a step */
+  CGKS_ESTATE = -5         /* call order: e.g. step before a state was set */
+};
+enum { CGKS_SCHEME_CGKS5 = 0, CGKS_SCHEME_GKS2 = 1 };
+/* CGKS5: LINEAR = P^4 everywhere, NONLINEAR = GENO everywhere, LEARNED = GENO where the troubled-cell
+ * network flags the cell.  GKS2: LINEAR = unlimited P^1, NONLINEAR = Venkatakrishnan limiter. */
+enum { CGKS_RECON_LINEAR = 0, CGKS_RECON_NONLINEAR = 1, CGKS_RECON_LEARNED = 2 };
+/* FP64: every step in double.  FP32_BULK: reconstruction, flux and gradient state in float;
+ * cell averages, their stage accumulations, Gauss-point states and cons->prim in double. */
+enum { CGKS_PREC_FP64 = 0, CGKS_PREC_FP32_BULK = 1 };
+enum { CGKS_IC_VORTEX2D = 0, CGKS_IC_TGV = 1, CGKS_IC_TGV_SUPERSONIC = 2 };
+
+typedef struct {
+  int nx, ny, nz;           /* cells per direction (>= 1; nz == 1 runs the 3-D scheme on a 2-D field) */
+  double lx, ly, lz;        /* box lengths; h_d = l_d / n_d */
+  double gamma;             /* ratio of specific heats (> 1); internal DOF K = (5 - 3 gamma)/(gamma - 1) */
+  double mu0;               /* reference viscosity; 0 selects the inviscid collision time (Sec. 4) */
+  double prandtl;           /* Prandtl number (1 or <= 0: no heat-flux correction) */
+  double sutherland_tref;   /* > 0: mu = mu0 1.4042 th^1.5/(th + 0.4042), th = T/tref (Sec. 4.2); else mu0 */
+  double tau_eps;           /* inviscid collision-time factor (paper: 0.05) */
+  double tau_c;             /* pressure-jump factor C of the collision time (paper: 10) */
+  double vk_k;              /* Venkatakrishnan constant K, eps^2 = (K h)^3 (GKS2 NONLINEAR) */
+  double geno_dh;           /* GENO linear weight of the high-order polynomial (0.85) */
+  double geno_eps;          /* GENO epsilon (paper: 1e-15) */
+  int scheme;               /* CGKS_SCHEME_* */
+  int recon;                /* CGKS_RECON_* */
+  int precision;            /* CGKS_PREC_* */
+  double indicator_logit;   /* LEARNED: GENO iff the network's logit exceeds this */
+} cgks_params;
+
+/* Diagnostics of the current state (Sec. 4.1, 4.2): one-point quadrature of the cell averages;
+ * velocity gradients from the cell-averaged gradients ((grad m - U grad rho)/rho; GKS2 uses central
+ * differences).  Ek, epsS, epsD, epsT normalised by rho0 u0^2 and the cell count. */
+typedef struct {
+  double Ek, epsS, epsD, epsT;
+  double mass, momx, momy, momz, energy; /* sums of Q |Omega_i| */
+  double rho_min, p_min;
+  double flagged_fraction;               /* cells that ran GENO in the last stage (1 unless LEARNED) */
+  double t;
+  double step;
+  double reserved[2];
+} cgks_diag;
+
+/* Device bytes the caller must provide for these parameters (EINVAL on bad parameters). */
+int cgks_workspace_bytes(const cgks_params* p, size_t* bytes);
+
+/* Create a context on the current HIP device.  dev_workspace: device pointer of >= the bytes above,
+ * 256-byte aligned; hip_stream: a hipStream_t (NULL = the null stream). */
+int cgks_create(const cgks_params* p, void* dev_workspace, size_t bytes, void* hip_stream, void** ctx);
+int cgks_destroy(void* ctx);
+
+/* Set the state from host arrays q[5N], g[15N] (g may be NULL: zero gradients; GKS2 ignores g). */
+int cgks_set_state(void* ctx, const double* q, const double* g, double t, long step);
+/* Initial condition evaluated on the device: cell averages by 4x4x4 Gauss-Legendre quadrature and
+ * gradients by Gauss's theorem with 4x4 points per face.  prm: VORTEX2D {strength}; TGV {Ma, rho0,
+ * u0}; TGV_SUPERSONIC {Ma}.  The box is [0, l_x] x [0, l_y] x [0, l_z]. */
+int cgks_set_ic(void* ctx, int kind, const double* prm, int nprm);
+/* Copy the state to host arrays (double).  Synchronous. */
+int cgks_get_state(void* ctx, double* q, double* g, double* t, long* step);
+
+/* The time step the next cgks_step would take at this CFL number. */
+int cgks_compute_dt(void* ctx, double cfl, double* dt);
+/* Advance nsteps steps at CFL number cfl; when t_stop > 0 the last step is shortened to end at
+ * t_stop and stepping stops there.  *steps_done / *t_now report progress (also on error).
+ * ENONPHYSICAL leaves the state as it was at the start of the failing step. */
+int cgks_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done, double* t_now);
+/* Advance nsteps steps of the given dt (no CFL evaluation). */
+int cgks_step_fixed(void* ctx, int nsteps, double dt);
+/* One stage operator on the current state with step size dt, copied to host arrays (any may be
+ * NULL): L[5N], dL/dt[5N] and, for CGKS5, the Gauss-theorem sums sqn[15N], sqt[15N] of the
+ * interface values and of their time derivatives.  The state is unchanged. */
+int cgks_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double* sqt);
+
+int cgks_diagnostics(void* ctx, double rho0, double u0, cgks_diag* out);
+/* GENO flags (1 byte per cell) used by the last stage. */
+int cgks_get_flags(void* ctx, unsigned char* flags);
+
+/* ---- troubled-cell network (the learned form of the indicator) -------------------------------------
+ * 64 inputs (54 used) -> 32 -> 32 -> 32 -> 1, ReLU, logit output; params[4225] float:
+ * W1[32][64], b1[32], W2[32][32], b2[32], W3[32][32], b3[32], w4[32], b4.  Hidden layers run on BF16
+ * matrix cores with FP32 accumulation.  Inputs: for rho and rho E, along each axis, the values of the
+ * cells i-2..i+2 minus the centre value and h dQ/dx of the same five cells, over
+ * s = max|difference| + max|h dQ| + 1e-12 |Q_i|. */
+int cgks_indicator_set(void* ctx, const float* params, size_t n, double logit_threshold);
+int cgks_indicator_get(void* ctx, float* params, size_t n);
+/* Features of every cell of the current state (N x 64 float, host). */
+int cgks_features(void* ctx, float* out);
+/* Logits of the current network for every cell of the current state (host, N floats). */
+int cgks_indicator_logits(void* ctx, float* out);
+/* Labels of the current state: 1 iff max over the variables of |1 - chi| > thr under full GENO. */
+int cgks_labels(void* ctx, double thr, unsigned char* out);
+/* Train the network on device samples x[n][64] (bfloat16 bits) and labels y[n] (float 0/1) with
+ * mean binary cross-entropy and Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8), minibatch 1024,
+ * samples visited in a seeded permutation each epoch.  Weights start from the current parameters.
+ * dev_x / dev_y are caller-owned device pointers.  *final_loss: mean loss of the last epoch. */
+int cgks_indicator_train(void* ctx, const void* dev_x, const void* dev_y, long n, int epochs,
+                         double lr, uint64_t seed, double* final_loss);
+/* Loss and gradient of the current parameters on device samples (host output grad[4225]). */
+int cgks_indicator_grad(void* ctx, const void* dev_x, const void* dev_y, long n, double* loss,
+                        double* grad);
+
+/* ---- kernel timing ---------------------------------------------------------------------------------
+ * When enabled, every kernel launch of the sweep is bracketed by HIP events on the context's stream.
+ * cgks_timing_read synchronises the stream and returns, per kernel class, the number of launches and
+ * their summed duration in ms since the previous read (then resets).  Classes (CGKS_KC_*): 0 time-step
+ * reduction, 1 indicator inference, 2 reconstruction coefficients, 3 face flux, 4 stage update. */
+enum { CGKS_KC_DT = 0, CGKS_KC_INFER = 1, CGKS_KC_COEF = 2, CGKS_KC_FLUX = 3, CGKS_KC_UPDATE = 4,
+       CGKS_KC_COUNT = 5 };
+int cgks_timing_enable(void* ctx, int on);
+int cgks_timing_read(void* ctx, long* count, double* ms, int nclasses);
+
+/* ---- unit-parity hooks (the hot path's device routines on host-supplied inputs) ----------------------
+ * Gas-kinetic flux at n points in the face frame (first axis = normal), evaluated by the device
+ * routine of the sweep in the context's precision: wl/wr[n][20] = 5 conservative values then the
+ * derivatives along the normal and the two tangents (5 each); out[n][30] = F^n, F_t, Q^l_n, Q^l_t,
+ * Q^r_n, Q^r_t.  n <= 3 N (the face planes are the scratch).  Host arrays, synchronous. */
+int cgks_debug_point_flux(void* ctx, double dt, long n, const double* wl, const double* wr, double* out);
+/* The reconstruction coefficients of the current state as the sweep computes them (CGKS5):
+ * out[5][34][N] (double), basis order and normalisation of the generated tables (Sec. 3.2). */
+int cgks_debug_coefficients(void* ctx, double* out);
+
+const char* cgks_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

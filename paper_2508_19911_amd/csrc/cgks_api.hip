@@ -1,0 +1,761 @@
+// cgks_api.hip -- C ABI of libcgks.so (declared in include/cgks.h): context, workspace layout and
+// the per-step launch sequence of the CGKS-5th / GKS-2nd sweep on one MI355X.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cgks.h"
+#include "kernels.hpp"
+#include "mlp.hpp"
+
+using namespace cgks;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t Q, G, Qs, Gs, Acc, GQn, C, F, flags, red, scal, mlp, total;
+};
+
+bool valid(const cgks_params* p) {
+  if (!p) return false;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
+  if ((long long)p->nx * p->ny * p->nz > (1LL << 29)) return false;  // 32-bit byte offsets per plane
+  if (!(p->lx > 0) || !(p->ly > 0) || !(p->lz > 0) || !(p->gamma > 1.0)) return false;
+  if (p->scheme != CGKS_SCHEME_CGKS5 && p->scheme != CGKS_SCHEME_GKS2) return false;
+  if (p->recon < CGKS_RECON_LINEAR || p->recon > CGKS_RECON_LEARNED) return false;
+  if (p->scheme == CGKS_SCHEME_GKS2 && p->recon == CGKS_RECON_LEARNED) return false;
+  if (p->precision != CGKS_PREC_FP64 && p->precision != CGKS_PREC_FP32_BULK) return false;
+  if (p->mu0 < 0.0) return false;
+  return true;
+}
+
+Layout layout(const cgks_params* p) {
+  const size_t N = (size_t)p->nx * p->ny * p->nz;
+  const size_t ts = p->precision == CGKS_PREC_FP64 ? 8 : 4;
+  const bool c5 = p->scheme == CGKS_SCHEME_CGKS5;
+  const size_t nblk = (N + BLK - 1) / BLK;
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += align256(bytes);
+    return r;
+  };
+  L.Q = take(5 * N * 8);
+  L.G = take(15 * N * ts);
+  L.Qs = take(5 * N * 8);
+  L.Gs = take(15 * N * ts);
+  L.Acc = take(5 * N * 8);
+  L.GQn = take(15 * N * ts);
+  // coefficient planes: P^4 (34 per variable) or GKS-2nd slopes (3 per variable); at least 64
+  // floats per cell so the feature buffer of the indicator fits
+  size_t cbytes = (c5 ? 170 : 15) * N * ts;
+  if (cbytes < 64 * N * 4) cbytes = 64 * N * 4;
+  L.C = take(cbytes);
+  L.F = take((c5 ? 90 : 30) * N * ts);
+  L.flags = take(N);
+  L.red = take(nblk * 16 * 8);
+  L.scal = take(64 * 8);
+  L.mlp = take(mlp::workspace_bytes());
+  L.total = o;
+  return L;
+}
+
+struct Timing {
+  bool on = false;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> recs;
+};
+
+struct Ctx {
+  Timing tm;
+  cgks_params p;
+  Grid g;
+  Layout L;
+  char* ws;
+  hipStream_t stream;
+  FluxParams fp;
+  GenoParams gp;
+  double vk_eps2;
+  double t = 0.0;
+  long step = 0;
+  bool have_state = false;
+  bool have_mlp = false;
+  int nblk;
+  std::vector<float> mlp_host;
+  template <class T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+};
+
+int dev_error(const char* what, hipError_t e) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return CGKS_EDEVICE;
+}
+
+#define HIPCK(call)                                     \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return dev_error(#call, e_);  \
+  } while (0)
+
+#define LAUNCHCK(what)                                  \
+  do {                                                  \
+    hipError_t e_ = hipGetLastError();                  \
+    if (e_ != hipSuccess) return dev_error(what, e_);   \
+  } while (0)
+
+// ---------------------------------------------------------------------------- kernel timing
+hipEvent_t timing_event(Ctx& c) {
+  if (c.tm.pool.empty()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = c.tm.pool.back();
+  c.tm.pool.pop_back();
+  return e;
+}
+
+// brackets the launches issued in its scope with events (when timing is on)
+struct TimedScope {
+  Ctx& c;
+  int cls;
+  hipEvent_t a = nullptr;
+  TimedScope(Ctx& ctx, int k) : c(ctx), cls(k) {
+    if (c.tm.on && (a = timing_event(c))) hipEventRecord(a, c.stream);
+  }
+  ~TimedScope() {
+    if (!a) return;
+    hipEvent_t b = timing_event(c);
+    if (!b) return;
+    hipEventRecord(b, c.stream);
+    c.tm.recs.push_back({cls, a, b});
+  }
+};
+
+// ---------------------------------------------------------------------------- stage sequences
+template <class T>
+int run_flags(Ctx& c, const double* Q, const T* G) {
+  if (c.p.recon != CGKS_RECON_LEARNED) return CGKS_OK;
+  TimedScope ts(c, CGKS_KC_INFER);
+  return mlp::launch_infer<T>(c.g, Q, G, c.at<float>(c.L.mlp), c.at<unsigned char>(c.L.flags),
+                              nullptr, c.p.indicator_logit, c.at<char>(c.L.mlp), c.stream);
+}
+
+template <class T>
+int launch_coef(Ctx& c, const double* Q, const T* G) {
+  const dim3 grid(c.nblk), blk(BLK);
+  T* C = c.at<T>(c.L.C);
+  const unsigned char* fl = c.at<unsigned char>(c.L.flags);
+  TimedScope ts(c, CGKS_KC_COEF);
+  switch (c.p.recon) {
+    case CGKS_RECON_LINEAR: k_coef<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp); break;
+    case CGKS_RECON_NONLINEAR: k_coef<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp); break;
+    default: k_coef<T, 2><<<grid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp); break;
+  }
+  LAUNCHCK("k_coef");
+  return CGKS_OK;
+}
+
+// one CGKS-5th stage on (Q, G); STAGE 0 debug, 1 first, 2 second
+template <class T, int STAGE>
+int stage5(Ctx& c, const double* Q, const T* G, double dt) {
+  int rc = run_flags<T>(c, Q, G);
+  if (rc) return rc;
+  rc = launch_coef<T>(c, Q, G);
+  if (rc) return rc;
+  const dim3 grid(c.nblk), blk(BLK);
+  const dim3 fgrid((unsigned)((c.g.N + FACES_PER_BLK - 1) / FACES_PER_BLK));
+  const T* C = c.at<T>(c.L.C);
+  T* F = c.at<T>(c.L.F);
+  {
+    TimedScope t0(c, CGKS_KC_FLUX);
+    k_flux5<T, 0><<<fgrid, blk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
+  }
+  {
+    TimedScope t1(c, CGKS_KC_FLUX);
+    k_flux5<T, 1><<<fgrid, blk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
+  }
+  {
+    TimedScope t2(c, CGKS_KC_FLUX);
+    k_flux5<T, 2><<<fgrid, blk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
+  }
+  LAUNCHCK("k_flux5");
+  Stage5Out o;
+  o.Qs = c.at<double>(c.L.Qs);
+  o.Acc = c.at<double>(c.L.Acc);
+  o.GQn = c.at<T>(c.L.GQn);
+  o.Gs = c.at<T>(c.L.Gs);
+  o.Q = c.at<double>(c.L.Q);
+  o.G = c.at<T>(c.L.G);
+  {
+    TimedScope tu(c, CGKS_KC_UPDATE);
+    k_update5<T, STAGE><<<grid, blk, 0, c.stream>>>(c.g, F, c.at<double>(c.L.Q), o, dt);
+  }
+  LAUNCHCK("k_update5");
+  return CGKS_OK;
+}
+
+template <class T, int DEBUG>
+int stage2(Ctx& c, double dt) {
+  const dim3 grid(c.nblk), blk(BLK);
+  double* Q = c.at<double>(c.L.Q);
+  T* S = c.at<T>(c.L.C);
+  T* F = c.at<T>(c.L.F);
+  {
+    TimedScope ts(c, CGKS_KC_COEF);
+    if (c.p.recon == CGKS_RECON_NONLINEAR)
+      k_slopes2<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, S, c.vk_eps2);
+    else
+      k_slopes2<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, S, c.vk_eps2);
+  }
+  {
+    TimedScope t0(c, CGKS_KC_FLUX);
+    k_flux2<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, dt);
+  }
+  {
+    TimedScope t1(c, CGKS_KC_FLUX);
+    k_flux2<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, dt);
+  }
+  {
+    TimedScope t2(c, CGKS_KC_FLUX);
+    k_flux2<T, 2><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, dt);
+  }
+  {
+    TimedScope tu(c, CGKS_KC_UPDATE);
+    k_update2<T, DEBUG><<<grid, blk, 0, c.stream>>>(c.g, F, Q, c.at<double>(c.L.Acc),
+                                                     c.at<double>(c.L.Qs), dt);
+  }
+  LAUNCHCK("gks2 stage");
+  return CGKS_OK;
+}
+
+template <class T>
+int advance(Ctx& c, double dt) {
+  int rc;
+  if (c.p.scheme == CGKS_SCHEME_GKS2) return stage2<T, 0>(c, dt);
+  rc = stage5<T, 1>(c, c.at<double>(c.L.Q), c.at<T>(c.L.G), dt);
+  if (rc) return rc;
+  return stage5<T, 2>(c, c.at<double>(c.L.Qs), c.at<T>(c.L.Gs), dt);
+}
+
+int advance_any(Ctx& c, double dt) {
+  return c.p.precision == CGKS_PREC_FP64 ? advance<double>(c, dt) : advance<float>(c, dt);
+}
+
+// dt limits: out[0] = min h/(|U|+c), out[1] = max nu, out[2] = non-physical flag
+int dt_limits(Ctx& c, double out[3]) {
+  double* part = c.at<double>(c.L.red);
+  double* scal = c.at<double>(c.L.scal);
+  {
+    TimedScope ts(c, CGKS_KC_DT);
+    k_dt<<<c.nblk, BLK, 0, c.stream>>>(c.g, c.at<double>(c.L.Q), c.fp, part);
+    k_dt_final<<<1, BLK, 0, c.stream>>>(c.nblk, part, scal);
+  }
+  LAUNCHCK("k_dt");
+  HIPCK(hipMemcpyAsync(out, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  return CGKS_OK;
+}
+
+double dt_from_limits(const Ctx& c, const double lim[3], double cfl) {
+  double dt = cfl * lim[0];
+  if (c.p.mu0 > 0.0) {
+    const double hmin = std::fmin(c.g.h[0], std::fmin(c.g.h[1], c.g.h[2]));
+    dt = std::fmin(dt, cfl * hmin * hmin / (3.0 * lim[1]));
+  }
+  return dt;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+int cgks_workspace_bytes(const cgks_params* p, size_t* bytes) {
+  if (!valid(p) || !bytes) return CGKS_EINVAL;
+  *bytes = layout(p).total;
+  return CGKS_OK;
+}
+
+int cgks_create(const cgks_params* p, void* ws, size_t bytes, void* stream, void** out) {
+  if (!valid(p) || !out) return CGKS_EINVAL;
+  const Layout L = layout(p);
+  if (!ws || bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255)) return CGKS_EWORKSPACE;
+  Ctx* c = new Ctx;
+  c->p = *p;
+  c->L = L;
+  c->ws = static_cast<char*>(ws);
+  c->stream = static_cast<hipStream_t>(stream);
+  c->g.nx = p->nx;
+  c->g.ny = p->ny;
+  c->g.nz = p->nz;
+  c->g.N = (long long)p->nx * p->ny * p->nz;
+  c->g.h[0] = p->lx / p->nx;
+  c->g.h[1] = p->ly / p->ny;
+  c->g.h[2] = p->lz / p->nz;
+  for (int d = 0; d < 3; ++d) c->g.ih[d] = 1.0 / c->g.h[d];
+  c->fp.gamma = p->gamma;
+  c->fp.Kdof = (5.0 - 3.0 * p->gamma) / (p->gamma - 1.0);
+  c->fp.mu0 = p->mu0;
+  c->fp.tref = p->sutherland_tref;
+  c->fp.prandtl = p->prandtl;
+  c->fp.tau_eps = p->tau_eps;
+  c->fp.tau_c = p->tau_c;
+  c->gp.dH = p->geno_dh;
+  c->gp.eps = p->geno_eps;
+  const double hh = std::cbrt(c->g.h[0] * c->g.h[1] * c->g.h[2]);
+  c->vk_eps2 = std::pow(p->vk_k * hh, 3.0);
+  c->nblk = (int)((c->g.N + BLK - 1) / BLK);
+  // every cell runs GENO unless the indicator says otherwise
+  hipError_t e = hipMemsetAsync(c->ws + L.flags, 1, c->g.N, c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return dev_error("hipMemsetAsync", e);
+  }
+  *out = c;
+  return CGKS_OK;
+}
+
+int cgks_destroy(void* ctx) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return CGKS_OK;
+  hipStreamSynchronize(c->stream);
+  for (auto& r : c->tm.recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (auto e : c->tm.pool) hipEventDestroy(e);
+  delete c;
+  return CGKS_OK;
+}
+
+int cgks_timing_enable(void* ctx, int on) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  c.tm.on = on != 0;
+  return CGKS_OK;
+}
+
+int cgks_timing_read(void* ctx, long* count, double* ms, int nclasses) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!count || !ms || nclasses < 1) return CGKS_EINVAL;
+  for (int k = 0; k < nclasses; ++k) {
+    count[k] = 0;
+    ms[k] = 0.0;
+  }
+  HIPCK(hipStreamSynchronize(c.stream));
+  for (auto& r : c.tm.recs) {
+    float e = 0.0f;
+    HIPCK(hipEventElapsedTime(&e, r.a, r.b));
+    if (r.cls < nclasses) {
+      count[r.cls] += 1;
+      ms[r.cls] += e;
+    }
+    c.tm.pool.push_back(r.a);
+    c.tm.pool.push_back(r.b);
+  }
+  c.tm.recs.clear();
+  return CGKS_OK;
+}
+
+int cgks_set_state(void* ctx, const double* q, const double* g, double t, long step) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!q) return CGKS_EINVAL;
+  const size_t N = c.g.N;
+  HIPCK(hipMemcpyAsync(c.ws + c.L.Q, q, 5 * N * 8, hipMemcpyHostToDevice, c.stream));
+  if (c.p.precision == CGKS_PREC_FP64) {
+    if (g)
+      HIPCK(hipMemcpyAsync(c.ws + c.L.G, g, 15 * N * 8, hipMemcpyHostToDevice, c.stream));
+    else
+      HIPCK(hipMemsetAsync(c.ws + c.L.G, 0, 15 * N * 8, c.stream));
+  } else {
+    if (g) {
+      // stage through the face planes (>= 15 doubles per cell) and convert
+      HIPCK(hipMemcpyAsync(c.ws + c.L.F, g, 15 * N * 8, hipMemcpyHostToDevice, c.stream));
+      const long long n = 15LL * N;
+      k_convert<float><<<(unsigned)((n + BLK - 1) / BLK), BLK, 0, c.stream>>>(
+          n, c.at<double>(c.L.F), c.at<float>(c.L.G));
+      LAUNCHCK("k_convert");
+    } else {
+      HIPCK(hipMemsetAsync(c.ws + c.L.G, 0, 15 * N * 4, c.stream));
+    }
+  }
+  HIPCK(hipStreamSynchronize(c.stream));
+  c.t = t;
+  c.step = step;
+  c.have_state = true;
+  return CGKS_OK;
+}
+
+int cgks_set_ic(void* ctx, int kind, const double* prm, int nprm) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  ICParams ip;
+  ip.kind = kind;
+  ip.gamma = c.p.gamma;
+  ip.a0 = ip.a1 = ip.a2 = 0.0;
+  if (kind == CGKS_IC_VORTEX2D) {
+    ip.a0 = (prm && nprm > 0) ? prm[0] : 5.0;
+  } else if (kind == CGKS_IC_TGV) {
+    if (!prm || nprm < 3) return CGKS_EINVAL;
+    ip.a0 = prm[0];
+    ip.a1 = prm[1];
+    ip.a2 = prm[2];
+  } else if (kind == CGKS_IC_TGV_SUPERSONIC) {
+    if (!prm || nprm < 1) return CGKS_EINVAL;
+    ip.a0 = prm[0];
+  } else {
+    return CGKS_EINVAL;
+  }
+  if (c.p.precision == CGKS_PREC_FP64)
+    k_ic<double><<<c.nblk, BLK, 0, c.stream>>>(c.g, ip, c.at<double>(c.L.Q), c.at<double>(c.L.G));
+  else
+    k_ic<float><<<c.nblk, BLK, 0, c.stream>>>(c.g, ip, c.at<double>(c.L.Q), c.at<float>(c.L.G));
+  LAUNCHCK("k_ic");
+  HIPCK(hipStreamSynchronize(c.stream));
+  c.t = 0.0;
+  c.step = 0;
+  c.have_state = true;
+  return CGKS_OK;
+}
+
+int cgks_get_state(void* ctx, double* q, double* g, double* t, long* step) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_state) return CGKS_ESTATE;
+  const size_t N = c.g.N;
+  if (q) HIPCK(hipMemcpyAsync(q, c.ws + c.L.Q, 5 * N * 8, hipMemcpyDeviceToHost, c.stream));
+  std::vector<float> tmp;
+  if (g) {
+    if (c.p.precision == CGKS_PREC_FP64) {
+      HIPCK(hipMemcpyAsync(g, c.ws + c.L.G, 15 * N * 8, hipMemcpyDeviceToHost, c.stream));
+    } else {
+      tmp.resize(15 * N);
+      HIPCK(hipMemcpyAsync(tmp.data(), c.ws + c.L.G, 15 * N * 4, hipMemcpyDeviceToHost, c.stream));
+    }
+  }
+  HIPCK(hipStreamSynchronize(c.stream));
+  if (g && !tmp.empty())
+    for (size_t n = 0; n < 15 * N; ++n) g[n] = tmp[n];
+  if (t) *t = c.t;
+  if (step) *step = c.step;
+  return CGKS_OK;
+}
+
+int cgks_compute_dt(void* ctx, double cfl, double* dt) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_state) return CGKS_ESTATE;
+  if (!(cfl > 0.0) || !dt) return CGKS_EINVAL;
+  double lim[3];
+  int rc = dt_limits(c, lim);
+  if (rc) return rc;
+  if (lim[2] != 0.0) return CGKS_ENONPHYSICAL;
+  *dt = dt_from_limits(c, lim, cfl);
+  return CGKS_OK;
+}
+
+int cgks_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done, double* t_now) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  int done = 0, rc = CGKS_OK;
+  if (!c.have_state) rc = CGKS_ESTATE;
+  else if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) rc = CGKS_ESTATE;
+  else if (!(cfl > 0.0) || nsteps < 0) rc = CGKS_EINVAL;
+  for (; rc == CGKS_OK && done < nsteps; ++done) {
+    if (t_stop > 0.0 && c.t >= t_stop) break;
+    double lim[3];
+    rc = dt_limits(c, lim);
+    if (rc) break;
+    if (lim[2] != 0.0) {
+      rc = CGKS_ENONPHYSICAL;
+      break;
+    }
+    double dt = dt_from_limits(c, lim, cfl);
+    if (t_stop > 0.0 && c.t + dt > t_stop) dt = t_stop - c.t;
+    rc = advance_any(c, dt);
+    if (rc) break;
+    c.t += dt;
+    c.step += 1;
+  }
+  if (rc == CGKS_OK) {
+    hipError_t e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) rc = dev_error("hipStreamSynchronize", e);
+  }
+  if (steps_done) *steps_done = done;
+  if (t_now) *t_now = c.t;
+  return rc;
+}
+
+int cgks_step_fixed(void* ctx, int nsteps, double dt) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_state) return CGKS_ESTATE;
+  if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) return CGKS_ESTATE;
+  if (!(dt > 0.0) || nsteps < 0) return CGKS_EINVAL;
+  for (int s = 0; s < nsteps; ++s) {
+    int rc = advance_any(c, dt);
+    if (rc) return rc;
+    c.t += dt;
+    c.step += 1;
+  }
+  HIPCK(hipStreamSynchronize(c.stream));
+  return CGKS_OK;
+}
+
+int cgks_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double* sqt) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_state) return CGKS_ESTATE;
+  if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) return CGKS_ESTATE;
+  if (!(dt > 0.0)) return CGKS_EINVAL;
+  const bool f64 = c.p.precision == CGKS_PREC_FP64;
+  int rc;
+  if (c.p.scheme == CGKS_SCHEME_GKS2)
+    rc = f64 ? stage2<double, 1>(c, dt) : stage2<float, 1>(c, dt);
+  else if (f64)
+    rc = stage5<double, 0>(c, c.at<double>(c.L.Q), c.at<double>(c.L.G), dt);
+  else
+    rc = stage5<float, 0>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G), dt);
+  if (rc) return rc;
+  const size_t N = c.g.N;
+  if (L) HIPCK(hipMemcpyAsync(L, c.ws + c.L.Acc, 5 * N * 8, hipMemcpyDeviceToHost, c.stream));
+  if (Lt) HIPCK(hipMemcpyAsync(Lt, c.ws + c.L.Qs, 5 * N * 8, hipMemcpyDeviceToHost, c.stream));
+  std::vector<float> tn, tt;
+  if (c.p.scheme == CGKS_SCHEME_CGKS5) {
+    if (f64) {
+      if (sqn) HIPCK(hipMemcpyAsync(sqn, c.ws + c.L.GQn, 15 * N * 8, hipMemcpyDeviceToHost, c.stream));
+      if (sqt) HIPCK(hipMemcpyAsync(sqt, c.ws + c.L.Gs, 15 * N * 8, hipMemcpyDeviceToHost, c.stream));
+    } else {
+      if (sqn) {
+        tn.resize(15 * N);
+        HIPCK(hipMemcpyAsync(tn.data(), c.ws + c.L.GQn, 15 * N * 4, hipMemcpyDeviceToHost, c.stream));
+      }
+      if (sqt) {
+        tt.resize(15 * N);
+        HIPCK(hipMemcpyAsync(tt.data(), c.ws + c.L.Gs, 15 * N * 4, hipMemcpyDeviceToHost, c.stream));
+      }
+    }
+  }
+  HIPCK(hipStreamSynchronize(c.stream));
+  for (size_t n = 0; n < tn.size(); ++n) sqn[n] = tn[n];
+  for (size_t n = 0; n < tt.size(); ++n) sqt[n] = tt[n];
+  return CGKS_OK;
+}
+
+int cgks_diagnostics(void* ctx, double rho0, double u0, cgks_diag* out) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_state) return CGKS_ESTATE;
+  if (!out) return CGKS_EINVAL;
+  double* part = c.at<double>(c.L.red);
+  double* scal = c.at<double>(c.L.scal);
+  const double vol = c.g.h[0] * c.g.h[1] * c.g.h[2];
+  const unsigned char* fl = c.at<unsigned char>(c.L.flags);
+  const bool c5 = c.p.scheme == CGKS_SCHEME_CGKS5;
+  if (c.p.precision == CGKS_PREC_FP64) {
+    if (c5)
+      k_diag<double, 0><<<c.nblk, BLK, 0, c.stream>>>(c.g, c.at<double>(c.L.Q), c.at<double>(c.L.G), fl, c.fp, vol, part);
+    else
+      k_diag<double, 1><<<c.nblk, BLK, 0, c.stream>>>(c.g, c.at<double>(c.L.Q), c.at<double>(c.L.G), fl, c.fp, vol, part);
+  } else {
+    if (c5)
+      k_diag<float, 0><<<c.nblk, BLK, 0, c.stream>>>(c.g, c.at<double>(c.L.Q), c.at<float>(c.L.G), fl, c.fp, vol, part);
+    else
+      k_diag<float, 1><<<c.nblk, BLK, 0, c.stream>>>(c.g, c.at<double>(c.L.Q), c.at<float>(c.L.G), fl, c.fp, vol, part);
+  }
+  k_diag_final<<<1, BLK, 0, c.stream>>>(c.nblk, part, scal);
+  LAUNCHCK("k_diag");
+  double r[11];
+  HIPCK(hipMemcpyAsync(r, scal, 11 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  const double norm = 1.0 / (rho0 * u0 * u0 * (double)c.g.N);
+  out->Ek = r[0] * norm;
+  out->epsS = r[1] * norm;
+  out->epsD = 4.0 / 3.0 * r[2] * norm;
+  out->epsT = out->epsS + out->epsD;
+  out->mass = r[3];
+  out->momx = r[4];
+  out->momy = r[5];
+  out->momz = r[6];
+  out->energy = r[7];
+  out->flagged_fraction = r[8] / (double)c.g.N;
+  out->rho_min = r[9];
+  out->p_min = r[10];
+  out->t = c.t;
+  out->step = (double)c.step;
+  out->reserved[0] = out->reserved[1] = 0.0;
+  return CGKS_OK;
+}
+
+int cgks_get_flags(void* ctx, unsigned char* flags) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!flags) return CGKS_EINVAL;
+  HIPCK(hipMemcpyAsync(flags, c.ws + c.L.flags, c.g.N, hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  return CGKS_OK;
+}
+
+// ---------------------------------------------------------------------------- indicator
+int cgks_indicator_set(void* ctx, const float* params, size_t n, double logit_threshold) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!params || n != (size_t)mlp::NPARAM) return CGKS_EINVAL;
+  c.mlp_host.assign(params, params + n);
+  HIPCK(hipMemcpyAsync(c.ws + c.L.mlp, params, n * sizeof(float), hipMemcpyHostToDevice, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  c.p.indicator_logit = logit_threshold;
+  c.have_mlp = true;
+  return CGKS_OK;
+}
+
+int cgks_indicator_get(void* ctx, float* params, size_t n) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!params || n != (size_t)mlp::NPARAM) return CGKS_EINVAL;
+  if (!c.have_mlp) return CGKS_ESTATE;
+  HIPCK(hipMemcpyAsync(params, c.ws + c.L.mlp, n * sizeof(float), hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  return CGKS_OK;
+}
+
+int cgks_features(void* ctx, float* out) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_state) return CGKS_ESTATE;
+  if (!out || c.p.scheme != CGKS_SCHEME_CGKS5) return CGKS_EINVAL;
+  float* buf = c.at<float>(c.L.C);
+  int rc;
+  if (c.p.precision == CGKS_PREC_FP64)
+    rc = mlp::launch_features<double>(c.g, c.at<double>(c.L.Q), c.at<double>(c.L.G), buf, c.stream);
+  else
+    rc = mlp::launch_features<float>(c.g, c.at<double>(c.L.Q), c.at<float>(c.L.G), buf, c.stream);
+  if (rc) return rc;
+  HIPCK(hipMemcpyAsync(out, buf, (size_t)c.g.N * 64 * sizeof(float), hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  return CGKS_OK;
+}
+
+int cgks_indicator_logits(void* ctx, float* out) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_state || !c.have_mlp) return CGKS_ESTATE;
+  if (!out || c.p.scheme != CGKS_SCHEME_CGKS5) return CGKS_EINVAL;
+  float* logits = c.at<float>(c.L.C);
+  int rc;
+  if (c.p.precision == CGKS_PREC_FP64)
+    rc = mlp::launch_infer<double>(c.g, c.at<double>(c.L.Q), c.at<double>(c.L.G), c.at<float>(c.L.mlp),
+                                   c.at<unsigned char>(c.L.flags), logits, c.p.indicator_logit,
+                                   c.at<char>(c.L.mlp), c.stream);
+  else
+    rc = mlp::launch_infer<float>(c.g, c.at<double>(c.L.Q), c.at<float>(c.L.G), c.at<float>(c.L.mlp),
+                                  c.at<unsigned char>(c.L.flags), logits, c.p.indicator_logit,
+                                  c.at<char>(c.L.mlp), c.stream);
+  if (rc) return rc;
+  HIPCK(hipMemcpyAsync(out, logits, (size_t)c.g.N * sizeof(float), hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  return CGKS_OK;
+}
+
+int cgks_labels(void* ctx, double thr, unsigned char* out) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_state) return CGKS_ESTATE;
+  if (!out || c.p.scheme != CGKS_SCHEME_CGKS5) return CGKS_EINVAL;
+  unsigned char* buf = c.at<unsigned char>(c.L.C);
+  int rc;
+  if (c.p.precision == CGKS_PREC_FP64)
+    rc = mlp::launch_labels<double>(c.g, c.at<double>(c.L.Q), c.at<double>(c.L.G), c.gp, thr, buf, c.stream);
+  else
+    rc = mlp::launch_labels<float>(c.g, c.at<double>(c.L.Q), c.at<float>(c.L.G), c.gp, thr, buf, c.stream);
+  if (rc) return rc;
+  HIPCK(hipMemcpyAsync(out, buf, (size_t)c.g.N, hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  return CGKS_OK;
+}
+
+int cgks_indicator_train(void* ctx, const void* dev_x, const void* dev_y, long n, int epochs,
+                         double lr, uint64_t seed, double* final_loss) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_mlp) return CGKS_ESTATE;
+  if (!dev_x || !dev_y || n < 1 || epochs < 0 || !(lr > 0.0)) return CGKS_EINVAL;
+  double loss = 0.0;
+  int rc = mlp::train(c.at<char>(c.L.mlp), static_cast<const uint16_t*>(dev_x),
+                      static_cast<const float*>(dev_y), n, epochs, lr, seed, &loss, c.stream);
+  if (rc) return rc;
+  HIPCK(hipMemcpyAsync(c.mlp_host.data(), c.ws + c.L.mlp, mlp::NPARAM * sizeof(float),
+                       hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  if (final_loss) *final_loss = loss;
+  return CGKS_OK;
+}
+
+int cgks_indicator_grad(void* ctx, const void* dev_x, const void* dev_y, long n, double* loss,
+                        double* grad) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_mlp) return CGKS_ESTATE;
+  if (!dev_x || !dev_y || n < 1 || !grad) return CGKS_EINVAL;
+  return mlp::loss_grad(c.at<char>(c.L.mlp), static_cast<const uint16_t*>(dev_x),
+                        static_cast<const float*>(dev_y), n, loss, grad, c.stream);
+}
+
+int cgks_debug_point_flux(void* ctx, double dt, long n, const double* wl, const double* wr, double* out) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (n < 1 || !wl || !wr || !out || !(dt > 0.0)) return CGKS_EINVAL;
+  const size_t cap = (c.p.scheme == CGKS_SCHEME_CGKS5 ? 90 : 30) * (size_t)c.g.N *
+                     (c.p.precision == CGKS_PREC_FP64 ? 8 : 4);
+  if ((size_t)n * 70 * 8 > cap) return CGKS_EINVAL;
+  double* d = c.at<double>(c.L.F);
+  HIPCK(hipMemcpyAsync(d, wl, n * 20 * 8, hipMemcpyHostToDevice, c.stream));
+  HIPCK(hipMemcpyAsync(d + n * 20, wr, n * 20 * 8, hipMemcpyHostToDevice, c.stream));
+  const unsigned nb = (unsigned)((n + 63) / 64);
+  if (c.p.precision == CGKS_PREC_FP64)
+    k_point_flux<double><<<nb, 64, 0, c.stream>>>(n, d, d + n * 20, d + n * 40, c.fp, dt);
+  else
+    k_point_flux<float><<<nb, 64, 0, c.stream>>>(n, d, d + n * 20, d + n * 40, c.fp, dt);
+  LAUNCHCK("k_point_flux");
+  HIPCK(hipMemcpyAsync(out, d + n * 40, n * 30 * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  return CGKS_OK;
+}
+
+int cgks_debug_coefficients(void* ctx, double* out) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_state) return CGKS_ESTATE;
+  if (!out || c.p.scheme != CGKS_SCHEME_CGKS5) return CGKS_EINVAL;
+  if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) return CGKS_ESTATE;
+  const size_t n = 170 * (size_t)c.g.N;
+  int rc;
+  if (c.p.precision == CGKS_PREC_FP64) {
+    rc = run_flags<double>(c, c.at<double>(c.L.Q), c.at<double>(c.L.G));
+    if (!rc) rc = launch_coef<double>(c, c.at<double>(c.L.Q), c.at<double>(c.L.G));
+    if (rc) return rc;
+    HIPCK(hipMemcpyAsync(out, c.ws + c.L.C, n * 8, hipMemcpyDeviceToHost, c.stream));
+    HIPCK(hipStreamSynchronize(c.stream));
+  } else {
+    rc = run_flags<float>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G));
+    if (!rc) rc = launch_coef<float>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G));
+    if (rc) return rc;
+    std::vector<float> tmp(n);
+    HIPCK(hipMemcpyAsync(tmp.data(), c.ws + c.L.C, n * 4, hipMemcpyDeviceToHost, c.stream));
+    HIPCK(hipStreamSynchronize(c.stream));
+    for (size_t k = 0; k < n; ++k) out[k] = tmp[k];
+  }
+  return CGKS_OK;
+}
+
+const char* cgks_strerror(int code) {
+  switch (code) {
+    case CGKS_OK: return "ok";
+    case CGKS_EINVAL: return "invalid argument";
+    case CGKS_EWORKSPACE: return "workspace missing, too small or not 256-byte aligned";
+    case CGKS_EDEVICE: return g_last_error.empty() ? "HIP error" : g_last_error.c_str();
+    case CGKS_ENONPHYSICAL: return "non-physical state (rho <= 0, p <= 0 or NaN)";
+    case CGKS_ESTATE: return "call order: no state / no indicator set";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// common.hpp -- shared device helpers for the CGKS-5th / GKS-2nd kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+namespace cgks {
+
+// math in the bulk type: the device library's correctly-rounded / few-ulp routines
+__host__ __device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
+__host__ __device__ __forceinline__ float dsqrt(float x) { return sqrtf(x); }
+__host__ __device__ __forceinline__ double dexp(double x) { return exp(x); }
+__host__ __device__ __forceinline__ float dexp(float x) { return expf(x); }
+__host__ __device__ __forceinline__ double dexpm1(double x) { return expm1(x); }
+__host__ __device__ __forceinline__ float dexpm1(float x) { return expm1f(x); }
+__host__ __device__ __forceinline__ double derfc(double x) { return erfc(x); }
+__host__ __device__ __forceinline__ float derfc(float x) { return erfcf(x); }
+
+// conversion of a data value (not a constant) to the bulk type; the second argument only selects the
+// overload (a counting type can supply its own)
+template <class T>
+__host__ __device__ __forceinline__ T data_cast(double x, T*) {
+  return T(x);
+}
+template <class T>
+__host__ __device__ __forceinline__ T data(double x) {
+  return data_cast(x, static_cast<T*>(nullptr));
+}
+
+// Grid geometry and the periodic neighbour arithmetic.
+struct Grid {
+  int nx, ny, nz;
+  long long N;
+  double h[3];
+  double ih[3];
+};
+
+__host__ __device__ __forceinline__ int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+__host__ __device__ __forceinline__ int wrap_p(int i, int n) { return i == n - 1 ? 0 : i + 1; }
+__host__ __device__ __forceinline__ int wrap_o(int i, int o, int n) {
+  int r = i + o;
+  r = r < 0 ? r + n : r;
+  return r >= n ? r - n : r;
+}
+
+// Loads and stores as (uniform base pointer, 32-bit element index): the address is an SGPR pair plus
+// a zero-extended 32-bit VGPR byte offset, so no 64-bit per-lane address is kept live.  Every plane
+// holds fewer than 2^29 elements (checked when a context is created).
+template <class T>
+__host__ __device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
+}
+template <class T>
+__host__ __device__ __forceinline__ void st(T* __restrict__ base, uint32_t idx, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T)) = v;
+}
+
+// face-frame permutation: the face of axis d sees (normal, t1, t2) = axes (d, d+1, d+2) mod 3
+__host__ __device__ constexpr int perm(int d, int k) { return (d + k) % 3; }
+
+}  // namespace cgks

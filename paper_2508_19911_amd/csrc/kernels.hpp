@@ -1,0 +1,611 @@
+// kernels.hpp -- HIP kernels of the CGKS-5th / GKS-2nd stage sweep (gfx950).
+//
+// Per CGKS-5th stage (arXiv 2508.19911, Sec. 2-3):
+//   k_coef   one thread per cell: gather the 19-cell stencil, P^4 coefficients (optionally GENO
+//            blended) -> coefficient planes C[v*34+m][cell];
+//   k_flux5  one thread per Gauss point of the face on the low side of each cell (one launch per
+//            direction): both sides evaluated from the coefficients of the adjacent cells, the
+//            gas-kinetic flux, the 2x2 Gauss average over 4 lanes -> face planes F[dir*30+n][cell];
+//   k_update5 one thread per cell: L, dL/dt and the Gauss-theorem sums of the interface values
+//            from the six faces, then the two-stage update (Sec. 3.4).
+// GKS-2nd (Sec. 3.3): k_slopes2 (P^1 + Venkatakrishnan), k_flux2 (face midpoints), k_update2.
+// Reductions (time step, diagnostics) are two-pass and deterministic.
+#pragma once
+#include "common.hpp"
+#include "gks_flux.hpp"
+#include "recon.hpp"
+
+namespace cgks {
+
+constexpr int BLK = 256;
+
+__device__ __forceinline__ void cell_ijk(const Grid& g, int cell, int& i, int& j, int& k) {
+  i = cell % g.nx;
+  const int jk = cell / g.nx;
+  j = jk % g.ny;
+  k = jk / g.ny;
+}
+
+template <int DIR>
+__device__ __forceinline__ int neighbour_m(const Grid& g, int cell, int i, int j, int k) {
+  if constexpr (DIR == 0) return cell - i + wrap_m(i, g.nx);
+  if constexpr (DIR == 1) return cell + (wrap_m(j, g.ny) - j) * g.nx;
+  return cell + (wrap_m(k, g.nz) - k) * g.nx * g.ny;
+}
+template <int DIR>
+__device__ __forceinline__ int neighbour_p(const Grid& g, int cell, int i, int j, int k) {
+  if constexpr (DIR == 0) return cell - i + wrap_p(i, g.nx);
+  if constexpr (DIR == 1) return cell + (wrap_p(j, g.ny) - j) * g.nx;
+  return cell + (wrap_p(k, g.nz) - k) * g.nx * g.ny;
+}
+
+// ============================================================================ reconstruction
+// Gather the stencil of one variable and accumulate a = R d column by column; the face-neighbour
+// differences and the cell's own normalised gradient are kept for GENO.
+template <class T, int S = 0>
+__host__ __device__ __forceinline__ void gather_coefficients(const Grid& g, const double* __restrict__ Qv,
+                                                    const T* __restrict__ Gv, long long N,
+                                                    const int* sidx, double q0, T* a, T* dface,
+                                                    T* g0) {
+  if constexpr (S < tab::NSTEN) {
+    const uint32_t c = (uint32_t)sidx[S];
+    if constexpr (S != tab::CENTRE) {
+      const T x = data<T>(ld(Qv, c) - q0);
+      op_col<tab::NEIGH_SLOT[S]>(x, a);
+#pragma unroll
+      for (int f = 0; f < 6; ++f)
+        if (face_slot(f) == tab::NEIGH_SLOT[S]) dface[f] = x;
+    }
+    const T gx = T(g.h[0]) * ld(Gv, c), gy = T(g.h[1]) * ld(Gv + N, c),
+            gz = T(g.h[2]) * ld(Gv + 2 * N, c);
+    op_col<18 + 3 * S + 0>(gx, a);
+    op_col<18 + 3 * S + 1>(gy, a);
+    op_col<18 + 3 * S + 2>(gz, a);
+    if constexpr (S == tab::CENTRE) {
+      g0[0] = gx;
+      g0[1] = gy;
+      g0[2] = gz;
+    }
+#ifdef __HIP_DEVICE_COMPILE__
+    // one stencil cell at a time: the scheduler may not hoist its loads above the previous cell
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+    gather_coefficients<T, S + 1>(g, Qv, Gv, N, sidx, q0, a, dface, g0);
+  }
+}
+
+template <class T, int MODE>  // MODE 0 linear, 1 GENO everywhere, 2 GENO where flagged
+__global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__ Q,
+                                              const T* __restrict__ G,
+                                              const unsigned char* __restrict__ flags,
+                                              T* __restrict__ C, GenoParams gp) {
+  const int cell = blockIdx.x * BLK + threadIdx.x;
+  if (cell >= g.N) return;
+  int i, j, k;
+  cell_ijk(g, cell, i, j, k);
+  const long long N = g.N;
+  int sidx[tab::NSTEN];
+#pragma unroll
+  for (int s = 0; s < tab::NSTEN; ++s)
+    sidx[s] = (wrap_o(k, tab::SOFF[s][2], g.nz) * g.ny + wrap_o(j, tab::SOFF[s][1], g.ny)) * g.nx +
+              wrap_o(i, tab::SOFF[s][0], g.nx);
+  bool geno = MODE == 1;
+  if constexpr (MODE == 2) geno = flags[cell] != 0;
+#pragma unroll 1
+  for (int v = 0; v < 5; ++v) {
+    const double* Qv = Q + v * N;
+    T a[tab::NB], dface[6], g0[3];
+#pragma unroll
+    for (int m = 0; m < tab::NB; ++m) a[m] = T(0);
+    gather_coefficients<T>(g, Qv, G + v * N, 5 * N, sidx, ld(Qv, (uint32_t)cell), a, dface, g0);
+    if (MODE != 0 && geno) geno_blend(dface, g0, a, gp);
+#pragma unroll
+    for (int m = 0; m < tab::NB; ++m) st(C + (v * tab::NB + m) * N, (uint32_t)cell, a[m]);
+  }
+}
+
+// ============================================================================ CGKS-5th face flux
+// One thread per (face, Gauss point): 4 consecutive lanes hold the 4 Gauss points of the face on the
+// low side of one cell; 64 faces per block.  The 2x2 Gauss average is a 4-lane reduction.
+constexpr int FACES_PER_BLK = BLK / 4;
+
+template <class T, int DIR>
+__global__ __launch_bounds__(BLK) void k_flux5(Grid g, const double* __restrict__ Q,
+                                               const T* __restrict__ C, T* __restrict__ F,
+                                               FluxParams fp, double dt) {
+  const int kgp = threadIdx.x & 3;
+  int cell = blockIdx.x * FACES_PER_BLK + (threadIdx.x >> 2);
+  const bool active = cell < g.N;
+  if (!active) cell = g.N - 1;  // keep the lane in the reduction; its result is not stored
+  int i, j, k;
+  cell_ijk(g, cell, i, j, k);
+  const int left = neighbour_m<DIR>(g, cell, i, j, k);
+  const long long N = g.N;
+  // tangential signs of the Gauss points (-,-), (-,+), (+,-), (+,+)
+  static_assert(tab::GP_SIGN[0][0] == -1 && tab::GP_SIGN[1][1] == 1 && tab::GP_SIGN[2][0] == 1,
+                "Gauss point order");
+  const T s1 = T(kgp < 2 ? -1 : 1);
+  const T s2 = T((kgp & 1) ? 1 : -1);
+  double WL[5], WR[5];
+  T DL[15], DR[15];
+#pragma unroll
+  for (int vf = 0; vf < 5; ++vf) {
+    const int vg = (vf >= 1 && vf <= 3) ? 1 + perm(DIR, vf - 1) : vf;
+    T a[tab::NB], val, der[3];
+#pragma unroll
+    for (int m = 0; m < tab::NB; ++m) a[m] = ld(C + (vg * tab::NB + m) * N, (uint32_t)left);
+    eval_gp<2 * DIR + 1>(a, s1, s2, val, der);
+    WL[vf] = ld(Q + vg * N, (uint32_t)left) + double(val);
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) DL[dd * 5 + vf] = der[perm(DIR, dd)] * T(g.ih[perm(DIR, dd)]);
+#pragma unroll
+    for (int m = 0; m < tab::NB; ++m) a[m] = ld(C + (vg * tab::NB + m) * N, (uint32_t)cell);
+    eval_gp<2 * DIR>(a, s1, s2, val, der);
+    WR[vf] = ld(Q + vg * N, (uint32_t)cell) + double(val);
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) DR[dd * 5 + vf] = der[perm(DIR, dd)] * T(g.ih[perm(DIR, dd)]);
+    // one variable at a time: 68 coefficients live, not 340
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  T out[30];
+  gks_flux<T, 30>(fp, dt, WL, DL, WR, DR, out);
+  // 2x2 Gauss average over the four lanes of the face
+#pragma unroll
+  for (int n = 0; n < 30; ++n) {
+    T x = out[n];
+    x += __shfl_xor(x, 1, 64);
+    x += __shfl_xor(x, 2, 64);
+    out[n] = T(0.25) * x;
+  }
+  if (active) {
+#pragma unroll
+    for (int blk = 0; blk < 6; ++blk)
+#pragma unroll
+      for (int vf = 0; vf < 5; ++vf) {
+        const int vg = (vf >= 1 && vf <= 3) ? 1 + perm(DIR, vf - 1) : vf;
+        const int n = blk * 5 + vf;
+        if ((n & 3) == kgp) st(F + (DIR * 30 + blk * 5 + vg) * N, (uint32_t)cell, out[n]);
+      }
+  }
+}
+
+// ============================================================================ unit-parity hooks
+template <class T>
+__global__ __launch_bounds__(64) void k_point_flux(long long n, const double* __restrict__ wl,
+                                                   const double* __restrict__ wr,
+                                                   double* __restrict__ out, FluxParams fp,
+                                                   double dt) {
+  const long long p = (long long)blockIdx.x * 64 + threadIdx.x;
+  if (p >= n) return;
+  double WL[5], WR[5];
+  T DL[15], DR[15];
+  for (int v = 0; v < 5; ++v) {
+    WL[v] = wl[p * 20 + v];
+    WR[v] = wr[p * 20 + v];
+  }
+  for (int q = 0; q < 15; ++q) {
+    DL[q] = T(wl[p * 20 + 5 + q]);
+    DR[q] = T(wr[p * 20 + 5 + q]);
+  }
+  T o[30];
+  gks_flux<T, 30>(fp, dt, WL, DL, WR, DR, o);
+  for (int q = 0; q < 30; ++q) out[p * 30 + q] = double(o[q]);
+}
+
+// ============================================================================ CGKS-5th update
+struct Stage5Out {
+  double* Qs;   // stage 1: Q*;           debug: dL/dt
+  double* Acc;  // stage 1: Q^n + dt L + dt^2/6 L_t;  debug: L
+  void* GQn;    // stage 1: sum Q_n;      debug: sum Q_n
+  void* Gs;     // stage 1: grad*;        debug: sum Q_t
+  double* Q;    // stage 2: Q^{n+1}
+  void* G;      // stage 2: grad^{n+1}
+};
+
+template <class T, int STAGE>  // 0 debug, 1 first stage, 2 second stage
+__global__ __launch_bounds__(BLK) void k_update5(Grid g, const T* __restrict__ F,
+                                                 const double* __restrict__ Qn, Stage5Out o,
+                                                 double dt) {
+  const int cell = blockIdx.x * BLK + threadIdx.x;
+  if (cell >= g.N) return;
+  int i, j, k;
+  cell_ijk(g, cell, i, j, k);
+  const long long N = g.N;
+  const int cp[3] = {neighbour_p<0>(g, cell, i, j, k), neighbour_p<1>(g, cell, i, j, k),
+                     neighbour_p<2>(g, cell, i, j, k)};
+  T* GQn = static_cast<T*>(o.GQn);
+  T* Gs = static_cast<T*>(o.Gs);
+  T* Gf = static_cast<T*>(o.G);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double L = 0.0, Lt = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const T* Fd = F + (long long)(d * 30) * N;
+      L -= (double(Fd[v * N + cp[d]]) - double(Fd[v * N + cell])) * g.ih[d];
+      Lt -= (double(Fd[(5 + v) * N + cp[d]]) - double(Fd[(5 + v) * N + cell])) * g.ih[d];
+      // this cell is the left cell of its + face and the right cell of its - face
+      const double sn = (double(Fd[(10 + v) * N + cp[d]]) - double(Fd[(20 + v) * N + cell])) * g.ih[d];
+      const double st = (double(Fd[(15 + v) * N + cp[d]]) - double(Fd[(25 + v) * N + cell])) * g.ih[d];
+      const long long gi = (d * 5 + v) * N + cell;
+      if constexpr (STAGE == 0) {
+        GQn[gi] = T(sn);
+        Gs[gi] = T(st);
+      } else if constexpr (STAGE == 1) {
+        GQn[gi] = T(sn);
+        Gs[gi] = T(sn + 0.5 * dt * st);
+      } else {
+        Gf[gi] = T(double(GQn[gi]) + dt * st);
+      }
+    }
+    const long long qi = v * N + cell;
+    if constexpr (STAGE == 0) {
+      o.Acc[qi] = L;
+      o.Qs[qi] = Lt;
+    } else if constexpr (STAGE == 1) {
+      const double q = Qn[qi];
+      o.Qs[qi] = q + 0.5 * dt * L + 0.125 * dt * dt * Lt;
+      o.Acc[qi] = q + dt * L + dt * dt / 6.0 * Lt;
+    } else {
+      o.Q[qi] = o.Acc[qi] + dt * dt / 3.0 * Lt;
+    }
+  }
+}
+
+// ============================================================================ GKS-2nd
+template <class T, int LIM>
+__global__ __launch_bounds__(BLK) void k_slopes2(Grid g, const double* __restrict__ Q,
+                                                 T* __restrict__ S, double vk_eps2) {
+  const int cell = blockIdx.x * BLK + threadIdx.x;
+  if (cell >= g.N) return;
+  int i, j, k;
+  cell_ijk(g, cell, i, j, k);
+  const long long N = g.N;
+  const int nb[6] = {neighbour_m<0>(g, cell, i, j, k), neighbour_p<0>(g, cell, i, j, k),
+                     neighbour_m<1>(g, cell, i, j, k), neighbour_p<1>(g, cell, i, j, k),
+                     neighbour_m<2>(g, cell, i, j, k), neighbour_p<2>(g, cell, i, j, k)};
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double q0 = Q[v * N + cell];
+    double q[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) q[m] = Q[v * N + nb[m]];
+    double b[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) b[e] = 0.5 * (q[2 * e + 1] - q[2 * e]);
+    double phi = 1.0;
+    if constexpr (LIM) {
+      double qmax = q0, qmin = q0;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        qmax = fmax(qmax, q[m]);
+        qmin = fmin(qmin, q[m]);
+      }
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        const double d2 = ((f % 2) ? 0.5 : -0.5) * b[f / 2];
+        double pf = 1.0;
+        if (d2 != 0.0) {
+          const double d1 = d2 > 0.0 ? qmax - q0 : qmin - q0;
+          pf = ((d1 * d1 + vk_eps2) + 2.0 * d1 * d2) / (d1 * d1 + 2.0 * d2 * d2 + d1 * d2 + vk_eps2);
+        }
+        phi = fmin(phi, pf);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 3; ++e) S[(v * 3 + e) * N + cell] = T(phi * b[e]);
+  }
+}
+
+template <class T, int DIR>
+__global__ __launch_bounds__(BLK) void k_flux2(Grid g, const double* __restrict__ Q,
+                                               const T* __restrict__ S, T* __restrict__ F,
+                                               FluxParams fp, double dt) {
+  const int cell = blockIdx.x * BLK + threadIdx.x;
+  if (cell >= g.N) return;
+  int i, j, k;
+  cell_ijk(g, cell, i, j, k);
+  const int left = neighbour_m<DIR>(g, cell, i, j, k);
+  const long long N = g.N;
+  double WL[5], WR[5];
+  T DL[15], DR[15];
+#pragma unroll
+  for (int vf = 0; vf < 5; ++vf) {
+    const int vg = (vf >= 1 && vf <= 3) ? 1 + perm(DIR, vf - 1) : vf;
+    const T* Sv = S + (long long)(vg * 3) * N;
+    WL[vf] = Q[vg * N + left] + 0.5 * double(Sv[DIR * N + left]);
+    WR[vf] = Q[vg * N + cell] - 0.5 * double(Sv[DIR * N + cell]);
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) {
+      const int e = perm(DIR, dd);
+      DL[dd * 5 + vf] = Sv[e * N + left] * T(g.ih[e]);
+      DR[dd * 5 + vf] = Sv[e * N + cell] * T(g.ih[e]);
+    }
+  }
+  T out[10];
+  gks_flux<T, 10>(fp, dt, WL, DL, WR, DR, out);
+#pragma unroll
+  for (int blk = 0; blk < 2; ++blk)
+#pragma unroll
+    for (int vf = 0; vf < 5; ++vf) {
+      const int vg = (vf >= 1 && vf <= 3) ? 1 + perm(DIR, vf - 1) : vf;
+      F[(DIR * 10 + blk * 5 + vg) * N + cell] = out[blk * 5 + vf];
+    }
+}
+
+template <class T, int DEBUG>
+__global__ __launch_bounds__(BLK) void k_update2(Grid g, const T* __restrict__ F, double* Q,
+                                                 double* Lout, double* Ltout, double dt) {
+  const int cell = blockIdx.x * BLK + threadIdx.x;
+  if (cell >= g.N) return;
+  int i, j, k;
+  cell_ijk(g, cell, i, j, k);
+  const long long N = g.N;
+  const int cp[3] = {neighbour_p<0>(g, cell, i, j, k), neighbour_p<1>(g, cell, i, j, k),
+                     neighbour_p<2>(g, cell, i, j, k)};
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double L = 0.0, Lt = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const T* Fd = F + (long long)(d * 10) * N;
+      L -= (double(Fd[v * N + cp[d]]) - double(Fd[v * N + cell])) * g.ih[d];
+      Lt -= (double(Fd[(5 + v) * N + cp[d]]) - double(Fd[(5 + v) * N + cell])) * g.ih[d];
+    }
+    if constexpr (DEBUG) {
+      Lout[v * N + cell] = L;
+      Ltout[v * N + cell] = Lt;
+    } else {
+      Q[v * N + cell] += dt * L + 0.5 * dt * dt * Lt;
+    }
+  }
+}
+
+// ============================================================================ reductions
+// block reduction in shared memory (fixed tree: deterministic)
+template <int NV, class Op>
+__device__ __forceinline__ void block_reduce(double (*sh)[BLK], double* val, Op op) {
+#pragma unroll
+  for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = val[q];
+  __syncthreads();
+  for (int s = BLK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+#pragma unroll
+      for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = op(q, sh[q][threadIdx.x], sh[q][threadIdx.x + s]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) val[q] = sh[q][0];
+}
+
+struct DtOp {
+  __device__ double operator()(int q, double a, double b) const {
+    return q == 0 ? fmin(a, b) : fmax(a, b);
+  }
+};
+
+// per block: min_i min_d h_d/(|U_d|+c), max nu, any non-physical cell
+__global__ __launch_bounds__(BLK) void k_dt(Grid g, const double* __restrict__ Q, FluxParams fp,
+                                            double* part) {
+  __shared__ double sh[3][BLK];
+  const int cell = blockIdx.x * BLK + threadIdx.x;
+  double val[3] = {INFINITY, 0.0, 0.0};
+  if (cell < g.N) {
+    const long long N = g.N;
+    const double rho = Q[cell], mx = Q[N + cell], my = Q[2 * N + cell], mz = Q[3 * N + cell],
+                 E = Q[4 * N + cell];
+    const double U = mx / rho, V = my / rho, W = mz / rho;
+    const double p = (fp.gamma - 1.0) * (E - 0.5 * rho * (U * U + V * V + W * W));
+    const bool ok = rho > 0.0 && p > 0.0 && isfinite(p) && isfinite(U) && isfinite(V) && isfinite(W);
+    if (ok) {
+      const double c = sqrt(fp.gamma * p / rho);
+      val[0] = fmin(g.h[0] / (fabs(U) + c), fmin(g.h[1] / (fabs(V) + c), g.h[2] / (fabs(W) + c)));
+      if (fp.mu0 > 0.0) val[1] = viscosity<double>(fp, p / rho) / rho;
+    } else {
+      val[2] = 1.0;
+    }
+  }
+  block_reduce<3>(sh, val, DtOp{});
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 3 + 0] = val[0];
+    part[blockIdx.x * 3 + 1] = val[1];
+    part[blockIdx.x * 3 + 2] = val[2];
+  }
+}
+
+__global__ __launch_bounds__(BLK) void k_dt_final(int nblk, const double* __restrict__ part,
+                                                  double* out) {
+  __shared__ double sh[3][BLK];
+  double val[3] = {INFINITY, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += BLK) {
+    val[0] = fmin(val[0], part[b * 3 + 0]);
+    val[1] = fmax(val[1], part[b * 3 + 1]);
+    val[2] = fmax(val[2], part[b * 3 + 2]);
+  }
+  block_reduce<3>(sh, val, DtOp{});
+  if (threadIdx.x == 0) {
+    out[0] = val[0];
+    out[1] = val[1];
+    out[2] = val[2];
+  }
+}
+
+struct DiagOp {
+  __device__ double operator()(int q, double a, double b) const {
+    return (q == 9 || q == 10) ? fmin(a, b) : a + b;
+  }
+};
+
+// diagnostics partials: 0 ek, 1 es, 2 ed, 3..7 sum Q, 8 flagged, 9 rho min, 10 p min
+template <class T, int CENTRAL>
+__global__ __launch_bounds__(BLK) void k_diag(Grid g, const double* __restrict__ Q,
+                                              const T* __restrict__ G,
+                                              const unsigned char* __restrict__ flags,
+                                              FluxParams fp, double vol, double* part) {
+  __shared__ double sh[11][BLK];
+  const int cell = blockIdx.x * BLK + threadIdx.x;
+  double val[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, INFINITY, INFINITY};
+  if (cell < g.N) {
+    const long long N = g.N;
+    double q[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q[v] = Q[v * N + cell];
+    const double rho = q[0];
+    const double U[3] = {q[1] / rho, q[2] / rho, q[3] / rho};
+    const double p = (fp.gamma - 1.0) * (q[4] - 0.5 * rho * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
+    double gr[3][4];  // d(rho, m_x, m_y, m_z)/dx_d
+    if constexpr (CENTRAL) {
+      int i, j, k;
+      cell_ijk(g, cell, i, j, k);
+      const int mp[3][2] = {{neighbour_m<0>(g, cell, i, j, k), neighbour_p<0>(g, cell, i, j, k)},
+                            {neighbour_m<1>(g, cell, i, j, k), neighbour_p<1>(g, cell, i, j, k)},
+                            {neighbour_m<2>(g, cell, i, j, k), neighbour_p<2>(g, cell, i, j, k)}};
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          gr[d][v] = (Q[v * N + mp[d][1]] - Q[v * N + mp[d][0]]) / (2.0 * g.h[d]);
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gr[d][v] = double(G[(d * 5 + v) * N + cell]);
+    }
+    double du[3][3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) du[a][d] = (gr[d][1 + a] - U[a] * gr[d][0]) / rho;
+    const double wx = du[2][1] - du[1][2], wy = du[0][2] - du[2][0], wz = du[1][0] - du[0][1];
+    const double div = du[0][0] + du[1][1] + du[2][2];
+    const double mu = viscosity<double>(fp, p / rho);
+    val[0] = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / rho;
+    val[1] = mu * (wx * wx + wy * wy + wz * wz);
+    val[2] = mu * div * div;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) val[3 + v] = q[v] * vol;
+    val[8] = flags ? double(flags[cell] != 0) : 1.0;
+    val[9] = rho;
+    val[10] = p;
+  }
+  block_reduce<11>(sh, val, DiagOp{});
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 11; ++q) part[blockIdx.x * 11 + q] = val[q];
+}
+
+__global__ __launch_bounds__(BLK) void k_diag_final(int nblk, const double* __restrict__ part,
+                                                    double* out) {
+  __shared__ double sh[11][BLK];
+  double val[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, INFINITY, INFINITY};
+  for (int b = threadIdx.x; b < nblk; b += BLK)
+#pragma unroll
+    for (int q = 0; q < 11; ++q) val[q] = DiagOp{}(q, val[q], part[b * 11 + q]);
+  block_reduce<11>(sh, val, DiagOp{});
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 11; ++q) out[q] = val[q];
+}
+
+// ============================================================================ conversions
+template <class T>
+__global__ __launch_bounds__(BLK) void k_convert(long long n, const double* __restrict__ src,
+                                                 T* __restrict__ dst) {
+  const long long idx = (long long)blockIdx.x * BLK + threadIdx.x;
+  if (idx < n) dst[idx] = T(src[idx]);
+}
+
+// ============================================================================ initial conditions
+struct ICParams {
+  int kind;  // 0 vortex, 1 TGV, 2 supersonic TGV
+  double gamma;
+  double a0, a1, a2;  // vortex: strength; TGV: Ma, rho0, u0
+};
+
+__device__ __forceinline__ void ic_point(const ICParams& ip, const Grid& g, double x, double y,
+                                         double z, double* c) {
+  const double gm = ip.gamma;
+  double rho, u, v, w, p;
+  if (ip.kind == 0) {
+    const double Lx = g.h[0] * g.nx, Ly = g.h[1] * g.ny;
+    double dx = x - 0.5 * Lx, dy = y - 0.5 * Ly;
+    dx = dx - Lx * floor(dx / Lx + 0.5);
+    dy = dy - Ly * floor(dy / Ly + 0.5);
+    const double r2 = dx * dx + dy * dy;
+    const double f = ip.a0 / (2.0 * M_PI) * exp(0.5 * (1.0 - r2));
+    u = 1.0 - f * dy;
+    v = 1.0 + f * dx;
+    w = 0.0;
+    const double T = 1.0 - (gm - 1.0) * ip.a0 * ip.a0 / (8.0 * gm * M_PI * M_PI) * exp(1.0 - r2);
+    rho = pow(T, 1.0 / (gm - 1.0));
+    p = rho * T;
+  } else {
+    double rho0, u0, p0, amp;
+    if (ip.kind == 1) {
+      rho0 = ip.a1;
+      u0 = ip.a2;
+      p0 = rho0 * u0 * u0 / (gm * ip.a0 * ip.a0);
+      amp = gm * ip.a0 * ip.a0 / 16.0;
+    } else {
+      rho0 = 1.0;
+      p0 = 1.0;
+      u0 = sqrt(gm) * ip.a0;
+      amp = 1.0 / 16.0;
+    }
+    const double s = (cos(2.0 * x) + cos(2.0 * y)) * (cos(2.0 * z) + 2.0);
+    rho = rho0 * (1.0 + amp * s);
+    p = p0 * (1.0 + amp * s);
+    u = u0 * sin(x) * cos(y) * cos(z);
+    v = -u0 * cos(x) * sin(y) * cos(z);
+    w = 0.0;
+  }
+  c[0] = rho;
+  c[1] = rho * u;
+  c[2] = rho * v;
+  c[3] = rho * w;
+  c[4] = p / (gm - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
+}
+
+template <class T>
+__global__ __launch_bounds__(BLK) void k_ic(Grid g, ICParams ip, double* __restrict__ Q,
+                                            T* __restrict__ G) {
+  const int cell = blockIdx.x * BLK + threadIdx.x;
+  if (cell >= g.N) return;
+  int i, j, k;
+  cell_ijk(g, cell, i, j, k);
+  const long long N = g.N;
+  // 4-point Gauss-Legendre on [-1/2, 1/2]
+  const double xg[4] = {-0.43056815579702629, -0.16999052179242813, 0.16999052179242813,
+                        0.43056815579702629};
+  const double wg[4] = {0.17392742256872693, 0.32607257743127307, 0.32607257743127307,
+                        0.17392742256872693};
+  const double c0[3] = {(i + 0.5) * g.h[0], (j + 0.5) * g.h[1], (k + 0.5) * g.h[2]};
+  double avg[5] = {0, 0, 0, 0, 0};
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int c = 0; c < 4; ++c) {
+        double s[5];
+        ic_point(ip, g, c0[0] + g.h[0] * xg[c], c0[1] + g.h[1] * xg[b], c0[2] + g.h[2] * xg[a], s);
+        const double wt = wg[a] * wg[b] * wg[c];
+        for (int v = 0; v < 5; ++v) avg[v] += wt * s[v];
+      }
+  for (int v = 0; v < 5; ++v) Q[v * N + cell] = avg[v];
+  for (int d = 0; d < 3; ++d) {
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    double diff[5] = {0, 0, 0, 0, 0};
+    for (int sg = -1; sg <= 1; sg += 2)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          double x[3];
+          x[d] = c0[d] + 0.5 * sg * g.h[d];
+          x[t1] = c0[t1] + g.h[t1] * xg[a];
+          x[t2] = c0[t2] + g.h[t2] * xg[b];
+          double s[5];
+          ic_point(ip, g, x[0], x[1], x[2], s);
+          for (int v = 0; v < 5; ++v) diff[v] += sg * wg[a] * wg[b] * s[v];
+        }
+    for (int v = 0; v < 5; ++v) G[(d * 5 + v) * N + cell] = T(diff[v] / g.h[d]);
+  }
+}
+
+}  // namespace cgks

@@ -133,8 +133,12 @@ def vortex_field(case: Case, t: float = 0.0, strength: float = 5.0):
 def tgv_field(case: Case):
     g = case.gamma
     rho0, u0 = case.rho0, case.u0
-    p0 = case.sutherland_tref * rho0
-    amp = g * case.ma ** 2 / 16.0 if case.name == "tgv" else 1.0 / 16.0
+    if case.name == "tgv":
+        p0 = rho0 * u0 * u0 / (g * case.ma ** 2)
+        amp = g * case.ma ** 2 / 16.0
+    else:
+        p0 = 1.0
+        amp = 1.0 / 16.0
 
     def fn(x, y, z):
         s = (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0)

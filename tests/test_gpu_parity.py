@@ -1,0 +1,220 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+FP64 bar: <= 1e-12 relative, measured against each quantity's natural scale -- max|Q| for the
+state, max|Q| (|U|+c)/h for L, max|Q| (|U|+c)^2/h^2 for dL/dt, max|Q|/h for the gradient sums (the
+rounding floor of any FP64 implementation is ~1e-16 of these) -- and field by field in L2 with a floor
+at 1e-6 of the largest field (so identically-zero fields, rho W in 2-D, compare roundoff at the
+largest field's scale).  Grids span several blocks with ragged tails.  The FP32-bulk form is checked
+against the same oracle with a bar of O(100) float roundings at the same scales.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_19911_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def cg():
+    from paper_2508_19911_amd import cgks
+    return cgks
+
+
+def scales(case, q):
+    """Natural scales of the stage outputs: the rounding floor of any FP64 implementation is ~1e-16
+    of these.  L ~ Q (|U| + c) / h, dL/dt ~ L (|U| + c) / h, interface sums ~ Q / h and ~ Q (|U|+c)/h^2."""
+    rho = q[0]; U = q[1:4] / rho
+    p = (case.gamma - 1) * (q[4] - 0.5 * rho * (U ** 2).sum(0))
+    vmax = float((np.abs(U).max(0) + np.sqrt(case.gamma * p / rho)).max())
+    h = min(case.h)
+    qmax = float(np.abs(q).max())
+    return {"L": qmax * vmax / h, "Lt": qmax * vmax ** 2 / h ** 2, "sqn": qmax / h, "sqt": qmax * vmax / h ** 2,
+            "Q": qmax}
+
+
+def scaled_err(a, b, scale):
+    """max over elements of |a - b| / scale (scale: the quantity's natural magnitude)"""
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / scale)
+
+
+def field_err(a, b):
+    """max over fields of ||a_f - b_f||_2 / max(||b_f||_2, 1e-6 max_f ||b_f||_2): relative per field,
+    with fields far below the largest (identically zero ones, such as rho W in 2-D) compared at the
+    largest field's scale"""
+    a = np.asarray(a).reshape(a.shape[0], -1); b = np.asarray(b).reshape(b.shape[0], -1)
+    nb = np.sqrt((b ** 2).sum(axis=1))
+    floor = 1e-6 * max(nb.max(), 1e-300)
+    return float((np.sqrt(((a - b) ** 2).sum(axis=1)) / np.maximum(nb, floor)).max())
+
+
+def pair(case, state, precision=0, learned_params=None, logit_thr=0.0):
+    q, g = state
+    o = oracle.Oracle(oracle.params_from_config(case))
+    s = cg().Solver(case, precision=precision, indicator_logit=logit_thr)
+    if learned_params is not None:
+        o.indicator_set(learned_params, logit_thr)
+        s.indicator_set(learned_params, logit_thr)
+    o.set_state(q, g)
+    s.set_state(q, g)
+    return o, s
+
+
+CASES = {
+    "vortex16": lambda: (inputs.vortex_case(16), None),
+    "tgv8": lambda: (inputs.tgv_case(8), None),
+    "ragged_viscous": lambda: (inputs.tgv_case(8, ma=0.3).with_(nx=13, ny=7, nz=5, lx=3.1, ly=1.9, lz=1.3), 11),
+    "ragged_inviscid": lambda: (inputs.vortex_case(8).with_(nx=11, ny=9, nz=3, lz=2.0), 12),
+}
+
+
+def make_state(name):
+    case, seed = CASES[name]()
+    if seed is None:
+        return case, inputs.initial_state(case)
+    return case, inputs.seeded_smooth_state(case, seed=seed, amp=0.15)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("recon", [0, 1])
+def test_stage_fp64(name, recon):
+    case, st = make_state(name)
+    case = case.with_(recon=recon)
+    o, s = pair(case, st)
+    dt = o.compute_dt(0.5)
+    assert abs(s.compute_dt(0.5) - dt) <= 1e-15 * dt
+    ro = o.stage(dt)
+    rg = s.stage(dt)
+    sc = scales(case, st[0])
+    for k, (a, b) in enumerate(zip(rg, ro)):
+        key = ["L", "Lt", "sqn", "sqt"][k]
+        e = scaled_err(a, b, sc[key])
+        assert e <= 1e-12, (name, recon, key, e)
+
+
+@pytest.mark.parametrize("name,recon,nsteps", [("vortex16", 0, 20), ("vortex16", 1, 6), ("tgv8", 1, 4),
+                                               ("ragged_viscous", 1, 3), ("ragged_inviscid", 0, 3)])
+def test_steps_fp64(name, recon, nsteps):
+    case, st = make_state(name)
+    case = case.with_(recon=recon)
+    o, s = pair(case, st)
+    rc, done, t = o.step(nsteps, 0.5)
+    assert rc == 0
+    _, done_g, t_g = s.step(nsteps, 0.5)
+    assert done_g == done and abs(t_g - t) <= 1e-13 * t
+    qo, go, _, _ = o.get_state()
+    qg, gg, _, _ = s.get_state()
+    sc = scales(case, st[0])
+    # rounding differences accumulate at most linearly over the steps of a stable scheme
+    bar = 1e-12 * nsteps
+    assert scaled_err(qg, qo, sc["Q"]) <= bar
+    assert field_err(qg, qo) <= bar
+    assert scaled_err(gg, go, sc["sqn"]) <= bar
+
+
+@pytest.mark.parametrize("recon", [0, 1])
+def test_gks2_fp64(recon):
+    case, st = make_state("ragged_viscous")
+    case = case.with_(scheme=1, recon=recon)
+    o, s = pair(case, st)
+    dt = o.compute_dt(0.5)
+    Lo, Lto, _, _ = o.stage(dt)
+    Lg, Ltg, _, _ = s.stage(dt)
+    sc = scales(case, st[0])
+    assert scaled_err(Lg, Lo, sc["L"]) <= 1e-12 and scaled_err(Ltg, Lto, sc["Lt"]) <= 1e-12
+    o.step(5, 0.5); s.step(5, 0.5)
+    assert scaled_err(s.get_state()[0], o.get_state()[0], sc["Q"]) <= 1e-12
+    assert field_err(s.get_state()[0], o.get_state()[0]) <= 1e-12
+
+
+def test_diagnostics_fp64():
+    case, st = make_state("tgv8")
+    case = case.with_(recon=1)
+    o, s = pair(case, st)
+    o.step(2, 0.5); s.step(2, 0.5)
+    do = o.diagnostics(1.0, 1.0); dg = s.diagnostics(1.0, 1.0)
+    for k in ["Ek", "epsS", "epsD", "epsT", "mass", "energy", "rho_min", "p_min"]:
+        assert abs(dg[k] - do[k]) <= 1e-12 * max(abs(do[k]), 1e-30), (k, dg[k], do[k])
+    for k in ["momx", "momy", "momz"]:
+        assert abs(dg[k] - do[k]) <= 1e-12 * do["mass"]
+
+
+def test_fp32_bulk_against_oracle():
+    """FP32-bulk: float rounding of the flux (~2^-24 of the largest flux component) divided by h sets
+    the error of one stage operator; after a few steps the state error stays at that level."""
+    case, st = make_state("tgv8")
+    case = case.with_(recon=1)
+    o, s = pair(case, st, precision=1)
+    dt = o.compute_dt(0.5)
+    Lo, Lto, sno, sto = o.stage(dt)
+    Lg, Ltg, sng, stg = s.stage(dt)
+    sc = scales(case, st[0])
+    eps32 = 2.0 ** -24
+    # float rounding of O(100) flux terms: bar 100 eps32 at each quantity's natural scale
+    for key, a, b in [("L", Lg, Lo), ("Lt", Ltg, Lto), ("sqn", sng, sno), ("sqt", stg, sto)]:
+        e = scaled_err(a, b, sc[key])
+        assert e <= 100 * eps32, (key, e)
+    o.step(3, 0.5); s.step(3, 0.5)
+    e = scaled_err(s.get_state()[0], o.get_state()[0], sc["Q"])
+    assert e <= 10 * eps32, e
+
+
+def test_device_initial_condition_matches_inputs():
+    case = inputs.tgv_case(12, ma=0.1)
+    q, g = inputs.tgv_state(case)
+    s = cg().Solver(case)
+    s.set_ic(cg().IC_TGV, [case.ma, case.rho0, case.u0])
+    qg, gg, _, _ = s.get_state()
+    assert np.abs(qg - q).max() <= 1e-12 * np.abs(q).max()
+    assert np.abs(gg - g).max() <= 1e-11 * max(np.abs(g).max(), 1.0)
+    cv = inputs.vortex_case(16)
+    qv, gv = inputs.vortex_state(cv)
+    sv = cg().Solver(cv)
+    sv.set_ic(cg().IC_VORTEX2D, [5.0])
+    qg, gg, _, _ = sv.get_state()
+    assert np.abs(qg - qv).max() <= 1e-12 * np.abs(qv).max()
+    assert np.abs(gg - gv).max() <= 1e-11
+
+
+def test_free_stream_bitwise_and_determinism():
+    case = inputs.tgv_case(9).with_(recon=1, nx=9, ny=6, nz=5, ly=1.1, lz=0.7)
+    q, g = inputs.uniform_state(case, rho=1.1, u=(0.2, -0.3, 0.4), p=0.9)
+    s = cg().Solver(case)
+    s.set_state(q, g)
+    s.step(3, 0.5)
+    q1, g1, _, _ = s.get_state()
+    assert np.array_equal(q1, q) and not np.any(g1)
+    case2, st = make_state("ragged_viscous")
+    case2 = case2.with_(recon=1)
+    outs = []
+    for _ in range(2):
+        s = cg().Solver(case2)
+        s.set_state(*st)
+        s.step(3, 0.5)
+        outs.append(s.get_state())
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_nonphysical_reported_and_state_kept():
+    case = inputs.tgv_case(6, ma=0.3)
+    q, g = inputs.uniform_state(case)
+    q[4, 7] = -1.0
+    s = cg().Solver(case)
+    s.set_state(q, g)
+    rc, done, _ = s.step(2, 0.5, check=False)
+    assert rc == -4 and done == 0
+    assert np.array_equal(s.get_state()[0], q)
+
+
+def test_conservation_fp32_bulk():
+    case, st = make_state("ragged_viscous")
+    case = case.with_(recon=1)
+    s = cg().Solver(case, precision=1)
+    s.set_state(*st)
+    d0 = s.diagnostics()
+    s.step(5, 0.5)
+    d1 = s.diagnostics()
+    for k in ["mass", "momx", "momy", "momz", "energy"]:
+        assert abs(d1[k] - d0[k]) <= 1e-12 * abs(d0["energy"]), (k, d1[k] - d0[k])

@@ -1,0 +1,79 @@
+"""CPU-side checks of the HIP library: it loads, exports every entry point that include/cgks.h
+declares, validates parameters on the host, and its exact-rational reconstruction tables agree with
+the oracle's floating-point least-squares solve (two independent constructions of the same operator).
+No compute call runs here (no GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "cgks.h")).read()
+    return sorted(set(re.findall(r"\b(cgks_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2508_19911_amd import cgks
+    lib = cgks.load()
+    names = header_symbols()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(cgks.SYMBOLS) == names
+
+
+def test_workspace_size_and_parameter_validation():
+    from paper_2508_19911_amd import cgks, inputs
+    lib = cgks.load()
+    case = inputs.tgv_case(16)
+    p = cgks.params_from_case(case)
+    n = ctypes.c_size_t()
+    assert lib.cgks_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == 0
+    # FP64 CGKS-5th: 60 state doubles + 170 coefficient + 90 face planes per cell, plus small buffers
+    assert 320 * 8 * case.N <= n.value <= 320 * 8 * case.N + 4 * 1024 * 1024
+    p32 = cgks.params_from_case(case, precision=1)
+    n32 = ctypes.c_size_t()
+    assert lib.cgks_workspace_bytes(ctypes.byref(p32), ctypes.byref(n32)) == 0 and n32.value < n.value
+    bad = cgks.params_from_case(case.with_(nx=0))
+    assert lib.cgks_workspace_bytes(ctypes.byref(bad), ctypes.byref(n)) == -1
+    bad = cgks.params_from_case(case.with_(gamma=1.0))
+    assert lib.cgks_workspace_bytes(ctypes.byref(bad), ctypes.byref(n)) == -1
+    bad = cgks.params_from_case(case.with_(scheme=1, recon=2))
+    assert lib.cgks_workspace_bytes(ctypes.byref(bad), ctypes.byref(n)) == -1
+    assert lib.cgks_strerror(-4).decode().startswith("non-physical")
+
+
+def test_exact_tables_match_oracle_operator():
+    from paper_2508_19911_amd import gen_recon
+    R_exact, stencil, neigh, basis = gen_recon.exact_operator()
+    Ro = oracle.recon_operator()
+    off = [tuple(o) for o in oracle.stencil_offsets()]
+    # oracle basis order: by degree, then d1 descending, d2 descending
+    ob = [(a, b, dg - a - b) for dg in range(1, 5) for a in range(dg, -1, -1) for b in range(dg - a, -1, -1)]
+    assert sorted(ob) == sorted(basis)
+    worst = 0.0
+    for i, d in enumerate(basis):
+        io = ob.index(d)
+        for c in range(75):
+            if c < 18:
+                co = off.index(neigh[c]) - 1
+            else:
+                s, e = divmod(c - 18, 3)
+                co = 18 + 3 * off.index(stencil[s]) + e
+            worst = max(worst, abs(float(R_exact[i][c]) - Ro[io, co]))
+    assert worst <= 1e-12, worst
+    nnz = sum(1 for row in R_exact for v in row if v != 0)
+    assert nnz == 678
+
+
+def test_generated_header_is_current():
+    from paper_2508_19911_amd import gen_recon
+    path = os.path.join(ROOT, "paper_2508_19911_amd", "csrc", "recon_tables.hpp")
+    assert open(path).read() == gen_recon.generate()
