@@ -1,0 +1,175 @@
+"""Benchmark of the CGKS-5th stage sweep on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--grid 128]
+
+Workload: Taylor-Green vortex, Re 1600, Ma 0.1, Pr 0.72, Sutherland, periodic [0, 2pi]^3 at 128^3
+(the configuration the metric is quoted on), initial condition evaluated on the device.  A step is
+one CGKS-5th time step: the CFL/viscous time-step reduction and the two stages (reconstruction,
+gas-kinetic flux at the face Gauss points, update of averages and gradients).
+
+Metric: Mcell-stage updates/s = cells x 2 stages x K / timed seconds, for
+  * the headline form: FP32-bulk with the learned troubled-cell indicator (GENO where the network
+    flags a cell), or FP32-bulk GENO everywhere when no trained indicator is present;
+  * FP64 plain (GENO everywhere), measured beside it; the line reports the speedup and the relative
+    L2 difference of the two velocity fields after the same steps.
+The roofline object is for the face-flux kernel (the dominant one): algorithmic flops per launch
+(flops.json, counted from the kernel's own templates) over its mean launch time, taken with HIP events
+on the library's stream during the timed region.  cpu_baseline times the FP64 oracle on host cores
+over a bounded sample of the same flow.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector peaks (FP32 packed-math figure)
+HBM_PEAK_GBS = 8000.0
+
+
+def load_flops():
+    with open(os.path.join(ROOT, "paper_2508_19911_amd", "flops.json")) as f:
+        return json.load(f)
+
+
+def load_indicator():
+    path = os.path.join(ROOT, "paper_2508_19911_amd", "indicator.npz")
+    if not os.path.exists(path):
+        return None
+    import numpy as np
+    z = np.load(path)
+    return z["params"].astype("float32"), float(z["logit_threshold"])
+
+
+def run_variant(case, precision, steps, warmup, timing, indicator=None):
+    import numpy as np
+    import torch
+    from paper_2508_19911_amd import cgks
+
+    thr = indicator[1] if indicator is not None else 0.0
+    s = cgks.Solver(case, precision=precision, indicator_logit=thr)
+    if indicator is not None:
+        s.indicator_set(indicator[0], indicator[1])
+    s.set_ic(cgks.IC_TGV, [case.ma, case.rho0, case.u0])
+    s.step(warmup, case.cfl)
+    torch.cuda.synchronize()
+    if timing:
+        s.timing(True)
+        s.timing_read()
+    t0 = time.perf_counter()
+    _, done, t_now = s.step(steps, case.cfl)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = s.timing_read() if timing else None
+    s.timing(False)
+    diag = s.diagnostics(case.rho0, case.u0)
+    q, _, _, _ = s.get_state()
+    vel = q[1:4] / q[0]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return {"seconds": t1 - t0, "steps": done, "t": t_now, "kernels": kt, "diag": diag, "vel": vel}
+
+
+def cpu_baseline(n=48):
+    """The FP64 oracle (OpenMP over the host's cores) on one CGKS-5th GENO step of the same flow at n^3."""
+    import oracle
+    from paper_2508_19911_amd import inputs
+
+    case = inputs.tgv_case(n).with_(recon=1)
+    q, g = inputs.tgv_state(case)
+    o = oracle.Oracle(oracle.params_from_config(case))
+    o.set_state(q, g)
+    t0 = time.perf_counter()
+    rc, done, _ = o.step(1, case.cfl)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": case.N * 2 * done / dt / 1e6, "unit": "Mcell-stage/s", "cores": cores, "kind": "oracle",
+            "sample": f"TGV Re1600 Ma0.1 {n}^3, 1 CGKS-5th GENO FP64 step (2 stages), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sweep is not sharded across GPUs.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2508_19911_amd import cgks, inputs
+
+    cgks.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    flops = load_flops()
+    indicator = load_indicator()
+    n = args.grid
+    base = inputs.tgv_case(n, ma=0.1, re=1600.0, prandtl=0.72)
+    N = base.N
+
+    head_case = base.with_(recon=cgks.RECON_LEARNED if indicator is not None else cgks.RECON_NONLINEAR)
+    head = run_variant(head_case, cgks.PREC_FP32_BULK, args.steps, args.warmup, True, indicator)
+    rate = N * 2 * head["steps"] / head["seconds"] / 1e6
+
+    fp64 = None
+    if not args.no_fp64:
+        fp64 = run_variant(base.with_(recon=cgks.RECON_NONLINEAR), cgks.PREC_FP64, args.steps, args.warmup, True)
+
+    kc, kms = head["kernels"]["flux"]
+    flux_ms = kms / max(kc, 1)
+    per_cell = flops["flux_launch_per_cell"]
+    achieved = per_cell * N / (flux_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": None, "kernel": "k_flux5<float>",
+            "flops_per_launch": per_cell * N, "mean_launch_ms": round(flux_ms, 4)}
+    kernels = {k: {"launches": c, "ms": round(m, 3)} for k, (c, m) in head["kernels"].items()}
+
+    line = {
+        "metric": "Mcell-stage updates/s at 1 GPU, FP32+learned vs FP64 plain, at equal L2 error",
+        "value": round(rate, 3),
+        "unit": "Mcell-stage/s",
+        "n_gpus": 1,
+        "steps": head["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(head["seconds"] / head["steps"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (analytic Taylor-Green initial condition on the device)",
+        "config": {"workload": f"Taylor-Green vortex Re1600 Ma0.1 Pr0.72 {n}^3 CGKS-5th",
+                   "cells": N, "variant": "fp32_bulk+learned" if indicator is not None else "fp32_bulk+geno(no indicator)",
+                   "cfl": base.cfl},
+        "roofline": roof,
+        "kernels_ms": kernels,
+    }
+    if fp64 is not None:
+        rate64 = N * 2 * fp64["steps"] / fp64["seconds"] / 1e6
+        dv = np.sqrt(((head["vel"] - fp64["vel"]) ** 2).sum()) / np.sqrt((fp64["vel"] ** 2).sum())
+        line["fp64_plain"] = {"value": round(rate64, 3), "ms_per_step": round(fp64["seconds"] / fp64["steps"] * 1e3, 3),
+                              "speedup_of_value": round(rate / rate64, 3), "rel_l2_velocity_diff": float(dv)}
+        if fp64["kernels"]:
+            c64, m64 = fp64["kernels"]["flux"]
+            a64 = per_cell * N / (m64 / max(c64, 1) * 1e-3) / 1e12
+            line["fp64_plain"]["flux_roofline"] = {"achieved": round(a64, 3), "peak": PEAK_TFLOPS["fp64"],
+                                                   "frac": round(a64 / PEAK_TFLOPS["fp64"], 4)}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

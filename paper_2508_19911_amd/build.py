@@ -33,6 +33,25 @@ def generate_tables(force: bool = False) -> None:
         gen_recon.main()
 
 
+def count_flops(verbose: bool = True) -> dict:
+    """Compile csrc/flopcount.hip (host program over the device templates), run it, write flops.json."""
+    import json
+    bdir = os.path.join(os.path.dirname(HERE), "_build")
+    os.makedirs(bdir, exist_ok=True)
+    exe = os.path.join(bdir, "flopcount")
+    cmd = [HIPCC, "-O1", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-o", exe, os.path.join(CSRC, "flopcount.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    counts = json.loads(out)
+    with open(os.path.join(HERE, "flops.json"), "w") as f:
+        json.dump(counts, f, indent=1, sort_keys=True)
+        f.write("\n")
+    return counts
+
+
 def build(verbose: bool = True, extra=None) -> str:
     generate_tables()
     src = os.path.join(CSRC, "cgks_api.hip")
@@ -41,6 +60,7 @@ def build(verbose: bool = True, extra=None) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    count_flops(verbose)
     return LIB
 
 

@@ -77,3 +77,15 @@ def test_generated_header_is_current():
     from paper_2508_19911_amd import gen_recon
     path = os.path.join(ROOT, "paper_2508_19911_amd", "csrc", "recon_tables.hpp")
     assert open(path).read() == gen_recon.generate()
+
+
+def test_flop_counts_are_current():
+    """flops.json (used by bench.py for the roofline) equals a fresh count from the kernel templates."""
+    import json
+    from paper_2508_19911_amd import build
+    path = os.path.join(ROOT, "paper_2508_19911_amd", "flops.json")
+    stored = json.load(open(path))
+    fresh = build.count_flops(verbose=False)
+    assert fresh == stored
+    # the face flux dominates a stage: three launches per stage
+    assert 3 * fresh["flux_launch_per_cell"] > 0.8 * fresh["cell_stage_geno"]
