@@ -62,8 +62,10 @@ def lib():
         L.cgkso_point_flux.argtypes = [ctypes.POINTER(Params), D, P, P, P, P]
         L.cgkso_recon_operator.argtypes = [P]
         L.cgkso_stencil_offsets.argtypes = [P]
-        L.cgkso_recon_cell.argtypes = [ctypes.POINTER(Params), P, P, P, I, P, P]
+        L.cgkso_recon_cell.argtypes = [ctypes.POINTER(Params), P, P, P, D, I, P, P]
         L.cgkso_face_gauss_points.argtypes = [P]
+        L.cgkso_geno_scale.argtypes = [P, I]
+        L.cgkso_geno_scale.restype = D
         L.cgkso_indicator_set.argtypes = [P, P, ctypes.c_size_t, D]
         L.cgkso_features.argtypes = [P, P]
         L.cgkso_labels.argtypes = [P, D, P]
@@ -235,12 +237,19 @@ def face_gauss_points():
     return g
 
 
-def recon_cell(params: Params, q, g, h, mode):
+def recon_cell(params: Params, q, g, h, mode, scale=1.0):
+    """scale: the variable's magnitude squared (GENO smoothness floor eps + h_max^2 scale)."""
     q = np.ascontiguousarray(q, dtype=np.float64); g = np.ascontiguousarray(g, dtype=np.float64)
     h = np.ascontiguousarray(h, dtype=np.float64)
     out = np.zeros((6, 4, 4)); info = np.zeros(4)
-    lib().cgkso_recon_cell(ctypes.byref(params), _ptr(q), _ptr(g), _ptr(h), int(mode), _ptr(out), _ptr(info))
+    lib().cgkso_recon_cell(ctypes.byref(params), _ptr(q), _ptr(g), _ptr(h), float(scale), int(mode),
+                           _ptr(out), _ptr(info))
     return out, info
+
+
+def geno_scale(q5, v):
+    q5 = np.ascontiguousarray(q5, dtype=np.float64)
+    return lib().cgkso_geno_scale(_ptr(q5), int(v))
 
 
 def mlp_forward(params, x, bf16=True):

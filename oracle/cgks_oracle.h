@@ -86,13 +86,17 @@ void cgkso_recon_operator(double* coef);
 /* offsets[19][3]: the cell itself, the 6 face neighbours, the 12 edge neighbours. */
 void cgkso_stencil_offsets(int* offsets);
 /* One cell, one variable: q[19] cell averages, g[19][3] cell-averaged gradients (physical units)
- * on the stencil of cgkso_stencil_offsets; h[3] cell sizes.  Writes out[6][4][4]: 6 faces
+ * on the stencil of cgkso_stencil_offsets; h[3] cell sizes; scale: the variable's magnitude squared
+ * (the GENO smoothness floor is eps + h_max^2 scale).  Writes out[6][4][4]: 6 faces
  * (-x,+x,-y,+y,-z,+z), 4 Gauss points, (value, d/dx, d/dy, d/dz), and info[4] = chi, IS_H, IS_L, 0.
  * mode 0 linear, 1 GENO. */
 void cgkso_recon_cell(const cgkso_params* p, const double* q, const double* g, const double* h,
-                      int mode, double* out, double* info);
+                      double scale, int mode, double* out, double* info);
 /* Gauss point tangential offsets on a face (normalised units), gp[4][2]. */
 void cgkso_face_gauss_points(double* gp);
+/* The GENO scale of variable v (0..4) of the conservative cell average q5[5], the "scale" argument
+ * of cgkso_recon_cell: rho^2 for v = 0, 2 rho rhoE for the momenta, (rhoE)^2 for v = 4. */
+double cgkso_geno_scale(const double* q5, int v);
 
 /* ---- troubled-cell MLP (BF16 emulated, FP64 arithmetic) ----------------- */
 enum { CGKSO_MLP_NIN = 64, CGKSO_MLP_NH = 32, CGKSO_MLP_NPARAM = 4225 };

@@ -21,8 +21,11 @@ const double* recon_operator();  // [NB][NCOL]
 void face_gauss_points(double gp[4][2]);
 // Reconstruct one variable of one cell; q[19], g[19][3] physical-unit gradients.
 // out[6][4][4] = faces (-x,+x,-y,+y,-z,+z) x Gauss points x (value, d/dx, d/dy, d/dz).
+// scale: the variable's magnitude squared, for the smoothness floor of the GENO path function
 void recon_cell(const cgkso_params& P, const double* q, const double (*g)[3], const double h[3],
-                int mode, double out[6][4][4], double info[4]);
+                double scale, int mode, double out[6][4][4], double info[4]);
+// the GENO scale of variable v of the conservative state q[5]: rho^2, 2 rho rhoE, (rhoE)^2
+double geno_scale(const double* q5, int v);
 // GKS-2nd: one variable of one cell from q[7] (cell, -x,+x,-y,+y,-z,+z): face-centre values
 // and slopes, out[6][4].
 void recon_cell_gks2(const cgkso_params& P, const double* q7, const double h[3], int limited,

@@ -13,9 +13,12 @@
  *      tangential slopes from the target's own cell-averaged gradient;
  *  R4  GENO blend of eq. (weno-new): omega_m from the paper's formula, evaluated as
  *      1/sum_k((IS_m+eps)/(IS_k+eps))^5; chi = omega_H/d_H with the adaptive-order weights
- *      alpha_H = d_H(1+(tau_Z/(IS_H+eps))^2), alpha_L = (1-d_H)(1+(tau_Z/(IS_L+eps))^2),
+ *      alpha_H = d_H(1+(tau_Z/(IS_H+e_chi))^2), alpha_L = (1-d_H)(1+(tau_Z/(IS_L+e_chi))^2),
  *      tau_Z = |IS_H-IS_L|, IS_H = sum_{1<=|alpha|<=4} int (D^alpha P^4)^2 over the unit cell,
- *      IS_L = |sum_m omega_m b^m|^2; applied per conservative component.
+ *      IS_L = |sum_m omega_m b^m|^2; applied per conservative component.  e_chi = eps + h^2 S with
+ *      h the largest cell size and S the variable's scale (rho^2, 2 rho rhoE for a momentum,
+ *      (rhoE)^2): at smooth critical points both indicators are O(h^4) and a bare eps would let
+ *      chi leave 1 there (second order); a jump of relative size above h still sends chi to 0.
  * Each face carries 2x2 Gauss-Legendre points (weights 1/4, Sec. 2).
  *
  * GKS-2nd (Sec. 3.3): least-squares P^1 on the 7-cell stencil (central differences on a
@@ -201,7 +204,7 @@ static const double* is_gram() {
 }
 
 void recon_cell(const cgkso_params& P, const double* q, const double (*g)[3], const double h[3],
-                int mode, double out[6][4][4], double info[4]) {
+                double scale, int mode, double out[6][4][4], double info[4]) {
   const double* R = recon_operator();
   double data[NCOL];
   for (int n = 0; n < 18; ++n) data[n] = q[n + 1] - q[0];
@@ -241,8 +244,10 @@ void recon_cell(const cgkso_params& P, const double* q, const double (*g)[3], co
       for (int j = 0; j < NB; ++j) ISH += a[i] * G[i * NB + j] * a[j];
     const double dH = P.geno_dh;
     const double tz = std::fabs(ISH - ISL);
-    const double aH = dH * (1.0 + std::pow(tz / (ISH + eps), 2.0));
-    const double aL = (1.0 - dH) * (1.0 + std::pow(tz / (ISL + eps), 2.0));
+    const double hmax = std::fmax(h[0], std::fmax(h[1], h[2]));
+    const double echi = eps + hmax * hmax * scale;
+    const double aH = dH * (1.0 + std::pow(tz / (ISH + echi), 2.0));
+    const double aL = (1.0 - dH) * (1.0 + std::pow(tz / (ISL + echi), 2.0));
     chi = (aH / (aH + aL)) / dH;
   }
   if (info) {
@@ -266,6 +271,12 @@ void recon_cell(const cgkso_params& P, const double* q, const double (*g)[3], co
       out[f][k][0] = q[0] + chi * val + (1.0 - chi) * lin;
       for (int e = 0; e < 3; ++e) out[f][k][1 + e] = (chi * der[e] + (1.0 - chi) * bbar[e]) / h[e];
     }
+}
+
+double geno_scale(const double* q5, int v) {
+  if (v == 0) return q5[0] * q5[0];
+  if (v == 4) return q5[4] * q5[4];
+  return 2.0 * q5[0] * q5[4];
 }
 
 void recon_cell_gks2(const cgkso_params& P, const double* q7, const double h[3], int limited,
@@ -313,11 +324,13 @@ void cgkso_recon_operator(double* coef) {
 void cgkso_stencil_offsets(int* offsets) { stencil_offsets(reinterpret_cast<int(*)[3]>(offsets)); }
 
 void cgkso_recon_cell(const cgkso_params* p, const double* q, const double* g, const double* h,
-                      int mode, double* out, double* info) {
-  recon_cell(*p, q, reinterpret_cast<const double(*)[3]>(g), h, mode,
+                      double scale, int mode, double* out, double* info) {
+  recon_cell(*p, q, reinterpret_cast<const double(*)[3]>(g), h, scale, mode,
              reinterpret_cast<double(*)[4][4]>(out), info);
 }
 
 void cgkso_face_gauss_points(double* gp) { face_gauss_points(reinterpret_cast<double(*)[2]>(gp)); }
+
+double cgkso_geno_scale(const double* q5, int v) { return geno_scale(q5, v); }
 
 }  // extern "C"

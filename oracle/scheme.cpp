@@ -122,6 +122,8 @@ static void stage_cgks5(Ctx& c, const double* Q, const double* G, double dt, dou
         int mode = 0;
         if (P.recon == CGKSO_RECON_NONLINEAR) mode = 1;
         if (P.recon == CGKSO_RECON_LEARNED) mode = c.flags[ci] ? 1 : 0;
+        double q5[5];
+        for (int v = 0; v < 5; ++v) q5[v] = Q[v * N + ci];
         for (int v = 0; v < 5; ++v) {
           double q[NSTEN], g[NSTEN][3];
           for (int s = 0; s < NSTEN; ++s) {
@@ -129,7 +131,7 @@ static void stage_cgks5(Ctx& c, const double* Q, const double* G, double dt, dou
             for (int e = 0; e < 3; ++e) g[s][e] = G[(5 * e + v) * N + sc[s]];
           }
           double out[6][4][4];
-          recon_cell(P, q, g, c.h, mode, out, nullptr);
+          recon_cell(P, q, g, c.h, geno_scale(q5, v), mode, out, nullptr);
           for (int f = 0; f < 6; ++f)
             for (int gp = 0; gp < 4; ++gp)
               for (int o = 0; o < 4; ++o) rec[ci * 480 + ((f * 4 + gp) * 5 + v) * 4 + o] = out[f][gp][o];
@@ -528,6 +530,8 @@ int cgkso_labels(void* ctx, double thr, unsigned char* out) {
       for (long i = 0; i < P.nx; ++i) {
         const long ci = cell_index(*c, i, j, k);
         double worst = 0.0;
+        double q5[5];
+        for (int v = 0; v < 5; ++v) q5[v] = c->Q[v * N + ci];
         for (int v = 0; v < 5; ++v) {
           double q[NSTEN], g[NSTEN][3], o[6][4][4], info[4];
           for (int s = 0; s < NSTEN; ++s) {
@@ -535,7 +539,7 @@ int cgkso_labels(void* ctx, double thr, unsigned char* out) {
             q[s] = c->Q[v * N + cs];
             for (int e = 0; e < 3; ++e) g[s][e] = c->G[(5 * e + v) * N + cs];
           }
-          recon_cell(P, q, g, c->h, 1, o, info);
+          recon_cell(P, q, g, c->h, geno_scale(q5, v), 1, o, info);
           worst = std::fmax(worst, std::fabs(1.0 - info[0]));
         }
         out[ci] = worst > thr ? 1 : 0;

@@ -318,6 +318,10 @@ int cgks_create(const cgks_params* p, void* ws, size_t bytes, void* stream, void
   c->fp.tau_c = p->tau_c;
   c->gp.dH = p->geno_dh;
   c->gp.eps = p->geno_eps;
+  {
+    const double hm = std::fmax(c->g.h[0], std::fmax(c->g.h[1], c->g.h[2]));
+    c->gp.hmax2 = hm * hm;
+  }
   const double hh = std::cbrt(c->g.h[0] * c->g.h[1] * c->g.h[2]);
   c->vk_eps2 = std::pow(p->vk_k * hh, 3.0);
   c->nblk = (int)((c->g.N + BLK - 1) / BLK);

@@ -172,7 +172,7 @@ int main() {
   gather_coefficients<Fl>(g, Qv, Gv, N, sidx, Qv[13], a, dface, g0);
   const long long coef_var = fc::n_flop + 18;
   const long long geno_base = fc::n_flop;
-  geno_blend(dface, g0, a, GenoParams{0.85, 1e-15});
+  geno_blend(dface, g0, a, GenoParams{0.85, 1e-15, 0.01}, leaf(0.01));
   const long long geno_var = fc::n_flop - geno_base;
 
   // --- k_update5 per cell: per variable and direction L (3), Lt (3), two interface sums (3 each),

@@ -91,6 +91,9 @@ __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__
               wrap_o(i, tab::SOFF[s][0], g.nx);
   bool geno = MODE == 1;
   if constexpr (MODE == 2) geno = flags[cell] != 0;
+  double q5[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) q5[v] = ld(Q + v * N, (uint32_t)cell);
 #pragma unroll 1
   for (int v = 0; v < 5; ++v) {
     const double* Qv = Q + v * N;
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__
 #pragma unroll
     for (int m = 0; m < tab::NB; ++m) a[m] = T(0);
     gather_coefficients<T>(g, Qv, G + v * N, 5 * N, sidx, ld(Qv, (uint32_t)cell), a, dface, g0);
-    if (MODE != 0 && geno) geno_blend(dface, g0, a, gp);
+    if (MODE != 0 && geno) geno_blend(dface, g0, a, gp, data<T>(gp.eps + gp.hmax2 * geno_scale(q5, v)));
 #pragma unroll
     for (int m = 0; m < tab::NB; ++m) st(C + (v * tab::NB + m) * N, (uint32_t)cell, a[m]);
   }

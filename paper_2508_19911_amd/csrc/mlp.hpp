@@ -132,6 +132,9 @@ __global__ __launch_bounds__(256) void k_labels(Grid g, const double* __restrict
     sidx[s] = (wrap_o(k, tab::SOFF[s][2], g.nz) * g.ny + wrap_o(j, tab::SOFF[s][1], g.ny)) * g.nx +
               wrap_o(i, tab::SOFF[s][0], g.nx);
   double worst = 0.0;
+  double q5[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) q5[v] = Q[v * N + cell];
 #pragma unroll 1
   for (int v = 0; v < 5; ++v) {
     const double* Qv = Q + v * N;
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(256) void k_labels(Grid g, const double* __restrict
 #pragma unroll
     for (int m = 0; m < tab::NB; ++m) a[m] = T(0);
     gather_coefficients<T>(g, Qv, G + v * N, 5 * N, sidx, Qv[cell], a, dface, g0);
-    const T chi = geno_blend(dface, g0, a, gp);
+    const T chi = geno_blend(dface, g0, a, gp, data<T>(gp.eps + gp.hmax2 * geno_scale(q5, v)));
     worst = fmax(worst, fabs(1.0 - double(chi)));
   }
   out[cell] = worst > thr ? 1 : 0;

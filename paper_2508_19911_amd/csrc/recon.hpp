@@ -8,8 +8,10 @@
 // polynomial across face m takes the neighbour difference as its normal slope and the target's own
 // cell-averaged gradient as its tangential slopes; omega_m = d_m/(IS_m+eps)^5 normalised (paper),
 // evaluated relative to the smallest IS_m+eps so no power under- or overflows; chi = omega_H/d_H
-// with adaptive-order weights alpha_H = d_H (1 + (tz/(IS_H+eps))^2), alpha_L = (1-d_H)
-// (1 + (tz/(IS_L+eps))^2), tz = |IS_H - IS_L|.
+// with adaptive-order weights alpha_H = d_H (1 + (tz/(IS_H+e))^2), alpha_L = (1-d_H)
+// (1 + (tz/(IS_L+e))^2), tz = |IS_H - IS_L|, e = eps + h_max^2 S (S: rho^2, 2 rho rhoE for a
+// momentum, (rhoE)^2), which keeps chi at 1 at smooth critical points where both indicators are
+// O(h^4) while a jump of relative size above h still drives chi to 0.
 #pragma once
 #include <utility>
 
@@ -70,12 +72,20 @@ __host__ __device__ __forceinline__ T gram_form(const T* a, std::integer_sequenc
 struct GenoParams {
   double dH;
   double eps;
+  double hmax2;  // square of the largest cell size
 };
 
+// the magnitude scale S of variable v of a cell state (for the smoothness floor of chi)
+__host__ __device__ __forceinline__ double geno_scale(const double* q5, int v) {
+  return v == 0 ? q5[0] * q5[0] : (v == 4 ? q5[4] * q5[4] : 2.0 * q5[0] * q5[4]);
+}
+
 // GENO: blend the coefficients a (one conservative variable) in place.  dface[f]: Q(neighbour across
-// face f) - Q0 for f = (-x,+x,-y,+y,-z,+z); g0: the cell's own normalised gradient h_e dQ/dx_e.
+// face f) - Q0 for f = (-x,+x,-y,+y,-z,+z); g0: the cell's own normalised gradient h_e dQ/dx_e;
+// echi: eps + h_max^2 S, the floor of the indicators in the path function.
 template <class T>
-__host__ __device__ __forceinline__ T geno_blend(const T* dface, const T* g0, T* a, const GenoParams& gp) {
+__host__ __device__ __forceinline__ T geno_blend(const T* dface, const T* g0, T* a, const GenoParams& gp,
+                                                 T echi) {
   const T eps = T(gp.eps);
   T b[6][3], ISe[6];
 #pragma unroll
@@ -109,7 +119,7 @@ __host__ __device__ __forceinline__ T geno_blend(const T* dface, const T* g0, T*
   const T ISH = gram_form(a, std::make_integer_sequence<int, tab::NB>{});
   const T tz = fabs(ISH - ISL);
   const T dH = T(gp.dH);
-  const T xh = tz / (ISH + eps), xl = tz / (ISL + eps);
+  const T xh = tz / (ISH + echi), xl = tz / (ISL + echi);
   const T aH = dH * (T(1) + xh * xh);
   const T aL = (T(1) - dH) * (T(1) + xl * xl);
   const T chi = (aH / (aH + aL)) / dH;

@@ -81,7 +81,7 @@ def test_reconstruction_coefficients():
                     c2 = ((k + o[2]) % nz) * nx * ny + ((j + o[1]) % ny) * nx + (i + o[0]) % nx
                     qs[si] = q[v, c2]
                     gs[si] = [g[5 * e + v, c2] for e in range(3)]
-                ref, _ = oracle.recon_cell(P, qs, gs, h, recon)
+                ref, _ = oracle.recon_cell(P, qs, gs, h, recon, scale=oracle.geno_scale(q[:, cell], v))
                 a = C[v, :, cell]
                 for f in range(6):
                     for kk in range(4):

@@ -211,3 +211,29 @@ def test_geno_chi_is_one_when_selected_data_is_smooth():
         _, info = oracle.recon_cell(P, q, g, h, 1)
         chis.append(abs(1 - info[0]))
     assert chis[0] < 1e-2 and chis[1] < chis[0] / 8
+
+
+@pytest.mark.parametrize("k", [(1.0, 0.0, 0.0), (0.8, 0.6, 0.5)])
+def test_geno_smoothness_floor_at_smooth_extremum(k):
+    """At a smooth extremum every linear sub-stencil slope vanishes, so with the bare epsilon the
+    path function drops to the low-order blend (chi = 0) however fine the grid; with the floor
+    eps + h_max^2 S (S = the variable's magnitude squared) 1 - chi falls at least as h^5."""
+    k = np.array(k)
+    bare, floor = [], []
+    for h0 in (0.1, 0.05):
+        h = np.full(3, h0)
+        q, g = _trig_data(h, k, np.pi / 2)  # cos(k.x): extremum at the cell centre
+        q = q + 2.0
+        _, i0 = oracle.recon_cell(P, q, g, h, 1, scale=0.0)
+        _, i1 = oracle.recon_cell(P, q, g, h, 1, scale=4.0)
+        bare.append(1 - i0[0]); floor.append(1 - i1[0])
+    assert min(bare) > 0.5, bare
+    assert floor[0] < 1e-6 and floor[1] < floor[0] / 32, floor
+
+
+def test_geno_scale_definition():
+    q5 = np.array([1.2, 0.3, -0.1, 0.2, 2.5])
+    assert oracle.geno_scale(q5, 0) == 1.2 ** 2
+    assert oracle.geno_scale(q5, 4) == 2.5 ** 2
+    for v in (1, 2, 3):
+        assert oracle.geno_scale(q5, v) == 2 * 1.2 * 2.5

@@ -72,10 +72,12 @@ def test_vortex_exact_solution_short():
 
 
 @pytest.mark.slow
-def test_vortex_convergence_order():
-    """Fixed end time (about the time of 20 steps on 64^2), tau -> 0 (eps = 0): the Euler limit."""
+@pytest.mark.parametrize("recon", [0, 1])
+def test_vortex_convergence_order(recon):
+    """Fixed end time (about the time of 20 steps on 64^2), tau -> 0 (eps = 0): the Euler limit;
+    linear and GENO (the path function must keep chi at 1 at the smooth extrema of the vortex)."""
     t_end = 0.5
-    errs = [_vortex_errors(n, 0, tau_eps=0.0, t_end=t_end)[1] for n in (16, 32, 64)]
+    errs = [_vortex_errors(n, 0, tau_eps=0.0, recon=recon, t_end=t_end)[1] for n in (16, 32, 64)]
     order = math.log2(errs[1] / errs[2])
     assert order > 4.3, errs
 
