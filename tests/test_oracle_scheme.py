@@ -196,3 +196,26 @@ def test_nonphysical_state_reported():
     o = make(case); o.set_state(q, g)
     rc, done, _ = o.step(2, 0.5)
     assert rc == -4 and done == 0
+
+
+def test_tgv_initial_diagnostics_closed_forms():
+    """Taylor-Green initial field (Sec. 4.1): <|u|^2>/2 = 1/8 and <|omega|^2> = 3/4 for
+    u = (sin x cos y cos z, -cos x sin y cos z, 0), so E_k -> 1/8 and eps_S -> (3/4)/Re, with the
+    O(h^2) error of one-point quadrature on cell averages; the velocity is solenoidal (eps_D = 0 to
+    rounding); the box totals are those of the field (mass (2 pi)^3, zero momentum, energy
+    p0/(gamma-1) (2 pi)^3 + (2 pi)^3/8).  Ma 0.01 keeps the density variation at 1e-5."""
+    errs = []
+    for n in (16, 32):
+        case = inputs.tgv_case(n, ma=0.01)
+        q, g = inputs.tgv_state(case)
+        o = make(case); o.set_state(q, g)
+        d = o.diagnostics()
+        errs.append((d["Ek"] - 0.125, d["epsS"] / (0.75 * case.mu0) - 1))
+        vol = (2 * math.pi) ** 3
+        p0 = 1.0 / (1.4 * 0.01 ** 2)
+        assert abs(d["mass"] - vol) <= 1e-12 * vol
+        assert max(abs(d["momx"]), abs(d["momy"]), abs(d["momz"])) <= 1e-12 * vol
+        assert abs(d["energy"] - (p0 / 0.4 + 0.125) * vol) <= 1e-4 * vol  # the kinetic part to 1e-3
+        assert d["epsD"] <= 1e-12 * d["epsS"]
+    e16, e32 = np.array(errs[0]), np.array(errs[1])
+    assert np.all(np.abs(e32) < 1.5e-2) and np.all(np.abs(e16 / e32) > 3.5), errs
