@@ -55,9 +55,11 @@ Layout layout(const cgks_params* p) {
   L.Gs = take(15 * N * ts);
   L.Acc = take(5 * N * 8);
   L.GQn = take(15 * N * ts);
-  // coefficient planes: P^4 (34 per variable) or GKS-2nd slopes (3 per variable); at least 64
-  // floats per cell so the feature buffer of the indicator fits
-  size_t cbytes = (c5 ? 170 : 15) * N * ts;
+  // coefficients: P^4 blocks (34 per variable, in 16-byte chunks of 16-cell blocks) or GKS-2nd
+  // slope planes (3 per variable); at least 64 floats per cell so the indicator's features fit
+  size_t cbytes = c5 ? (ts == 8 ? (size_t)CoefBlock<double>::elements(N) * 8
+                                : (size_t)CoefBlock<float>::elements(N) * 4)
+                     : 15 * N * ts;
   if (cbytes < 64 * N * 4) cbytes = 64 * N * 4;
   L.C = take(cbytes);
   L.F = take((c5 ? 90 : 30) * N * ts);
@@ -179,20 +181,20 @@ int stage5(Ctx& c, const double* Q, const T* G, double dt) {
   rc = launch_coef<T>(c, Q, G);
   if (rc) return rc;
   const dim3 grid(c.nblk), blk(BLK);
-  const dim3 fgrid((unsigned)((c.g.N + FACES_PER_BLK - 1) / FACES_PER_BLK));
+  const dim3 fgrid((unsigned)((c.g.N + FLUX_FACES - 1) / FLUX_FACES)), fblk(FLUX_BLK);
   const T* C = c.at<T>(c.L.C);
   T* F = c.at<T>(c.L.F);
   {
     TimedScope t0(c, CGKS_KC_FLUX);
-    k_flux5<T, 0><<<fgrid, blk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
+    k_flux5<T, 0><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
   }
   {
     TimedScope t1(c, CGKS_KC_FLUX);
-    k_flux5<T, 1><<<fgrid, blk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
+    k_flux5<T, 1><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
   }
   {
     TimedScope t2(c, CGKS_KC_FLUX);
-    k_flux5<T, 2><<<fgrid, blk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
+    k_flux5<T, 2><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
   }
   LAUNCHCK("k_flux5");
   Stage5Out o;
@@ -309,13 +311,7 @@ int cgks_create(const cgks_params* p, void* ws, size_t bytes, void* stream, void
   c->g.h[1] = p->ly / p->ny;
   c->g.h[2] = p->lz / p->nz;
   for (int d = 0; d < 3; ++d) c->g.ih[d] = 1.0 / c->g.h[d];
-  c->fp.gamma = p->gamma;
-  c->fp.Kdof = (5.0 - 3.0 * p->gamma) / (p->gamma - 1.0);
-  c->fp.mu0 = p->mu0;
-  c->fp.tref = p->sutherland_tref;
-  c->fp.prandtl = p->prandtl;
-  c->fp.tau_eps = p->tau_eps;
-  c->fp.tau_c = p->tau_c;
+  c->fp = make_flux_params(p->gamma, p->mu0, p->sutherland_tref, p->prandtl, p->tau_eps, p->tau_c);
   c->gp.dH = p->geno_dh;
   c->gp.eps = p->geno_eps;
   {
@@ -725,29 +721,46 @@ int cgks_debug_point_flux(void* ctx, double dt, long n, const double* wl, const 
   return CGKS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// the coefficient blocks of the device, reordered to out[5][34][N]
+template <class T>
+int copy_coefficients(Ctx& c, double* out) {
+  using CB = CoefBlock<T>;
+  std::vector<T> tmp((size_t)CB::elements(c.g.N));
+  HIPCK(hipMemcpyAsync(tmp.data(), c.ws + c.L.C, tmp.size() * sizeof(T), hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  const long long N = c.g.N;
+  for (int v = 0; v < 5; ++v)
+    for (long long cell = 0; cell < N; ++cell) {
+      const long long b = CB::base(cell, v);
+      for (int m = 0; m < tab::NB; ++m)
+        out[((size_t)v * tab::NB + m) * N + cell] =
+            (double)tmp[b + (m / CB::PER) * CB::CHUNK_STRIDE + m % CB::PER];
+    }
+  return CGKS_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int cgks_debug_coefficients(void* ctx, double* out) {
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_state) return CGKS_ESTATE;
   if (!out || c.p.scheme != CGKS_SCHEME_CGKS5) return CGKS_EINVAL;
   if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) return CGKS_ESTATE;
-  const size_t n = 170 * (size_t)c.g.N;
   int rc;
   if (c.p.precision == CGKS_PREC_FP64) {
     rc = run_flags<double>(c, c.at<double>(c.L.Q), c.at<double>(c.L.G));
     if (!rc) rc = launch_coef<double>(c, c.at<double>(c.L.Q), c.at<double>(c.L.G));
     if (rc) return rc;
-    HIPCK(hipMemcpyAsync(out, c.ws + c.L.C, n * 8, hipMemcpyDeviceToHost, c.stream));
-    HIPCK(hipStreamSynchronize(c.stream));
-  } else {
-    rc = run_flags<float>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G));
-    if (!rc) rc = launch_coef<float>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G));
-    if (rc) return rc;
-    std::vector<float> tmp(n);
-    HIPCK(hipMemcpyAsync(tmp.data(), c.ws + c.L.C, n * 4, hipMemcpyDeviceToHost, c.stream));
-    HIPCK(hipStreamSynchronize(c.stream));
-    for (size_t k = 0; k < n; ++k) out[k] = tmp[k];
+    return copy_coefficients<double>(c, out);
   }
-  return CGKS_OK;
+  rc = run_flags<float>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G));
+  if (!rc) rc = launch_coef<float>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G));
+  if (rc) return rc;
+  return copy_coefficients<float>(c, out);
 }
 
 const char* cgks_strerror(int code) {

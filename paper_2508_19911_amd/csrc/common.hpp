@@ -16,6 +16,15 @@ __host__ __device__ __forceinline__ double dexpm1(double x) { return expm1(x); }
 __host__ __device__ __forceinline__ float dexpm1(float x) { return expm1f(x); }
 __host__ __device__ __forceinline__ double derfc(double x) { return erfc(x); }
 __host__ __device__ __forceinline__ float derfc(float x) { return erfcf(x); }
+// reciprocal in the bulk type: IEEE 1/x in FP64; the hardware reciprocal (1 ulp) in the FP32 form
+__host__ __device__ __forceinline__ double drcp(double x) { return 1.0 / x; }
+__host__ __device__ __forceinline__ float drcp(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
 
 // conversion of a data value (not a constant) to the bulk type; the second argument only selects the
 // overload (a counting type can supply its own)

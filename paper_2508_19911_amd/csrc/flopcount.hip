@@ -104,6 +104,7 @@ inline Fl dsqrt(Fl x) { return un('s', x, std::sqrt(x.v())); }
 inline Fl dexp(Fl x) { return un('e', x, std::exp(x.v())); }
 inline Fl dexpm1(Fl x) { return un('x', x, std::expm1(x.v())); }
 inline Fl derfc(Fl x) { return un('r', x, std::erfc(x.v())); }
+inline Fl drcp(Fl x) { return mkf('/', Fl(1.0), x, 1.0 / x.v()); }
 inline Fl dfma(Fl a, Fl b, Fl c) { return fma(a, b, c); }
 }  // namespace fc
 
@@ -128,30 +129,31 @@ static void reset() {
 }
 
 int main() {
-  // --- one Gauss-point flux (k_flux5 thread: both states from coefficients, the flux, the 4-lane
-  //     Gauss average and the 0.25 scaling of its 30 outputs)
-  FluxParams fp{1.4, 2.0, 6.25e-4, 71.43, 0.72, 0.05, 10.0};
+  // --- k_flux5 per face: the 10 (variable, side) polynomials at the 4 Gauss points, then per point
+  //     the flux, the 4-lane Gauss average and the 0.25 scaling of its 30 outputs
+  const FluxParams fp = make_flux_params(1.4, 6.25e-4, 71.43, 0.72, 0.05, 10.0);
   double WL[5] = {1.0, 0.3, 0.1, -0.2, 180.0}, WR[5] = {1.01, 0.31, 0.09, -0.21, 180.2};
   Fl DL[15], DR[15], out[30];
   Fl a[34];
   reset();
   for (int m = 0; m < 34; ++m) a[m] = leaf(1e-3 * (m + 1));
-  Fl val, der[3];
-  eval_gp<1>(a, Fl(1.0), Fl(-1.0), val, der);
-  const long long eval_gp_flops = fc::n_flop;
-  // state assembly per side and variable: Q0 + value (1), three derivative scalings (3)
-  const long long state_flops = 2 * 5 * (eval_gp_flops + 1 + 3);
+  Fl val[4], der[4][3];
+  eval_face<1>(a, leaf(-1.0), val, der);
+  const long long eval_face_flops = fc::n_flop;
+  // per face: 10 (variable, side) polynomials, each evaluated at the 4 points, plus per point
+  // Q0 + value (1) and three derivative scalings (3)
+  const long long state_face = 10 * (eval_face_flops + 4 * (1 + 3));
   reset();
   for (int q = 0; q < 15; ++q) {
     DL[q] = leaf(0.01 * (q + 1));
     DR[q] = leaf(0.011 * (q + 1));
   }
   gks_flux<Fl, 30>(fp, 1e-3, WL, DL, WR, DR, out);
-  // FP64 cons->prim of the two states: 1/rho, 3 velocities, p (8), lambda (2) = 14 per side
-  const long long flux_flops = fc::n_flop + 2 * 14;
+  // FP64 cons->prim of the two states: 1/rho, 3 velocities, p (8), var = p/rho (1) = 13 per side;
+  // the FP64 difference and sum of the two pressures in the relative jump: 2
+  const long long flux_flops = fc::n_flop + 2 * 13 + 2;
   const long long flux_trans = fc::n_trans;
   const long long reduce_flops = 30 * 3;  // two lane sums and the 1/4 scaling per output
-  const long long per_gp = state_flops + flux_flops + reduce_flops;
 
   // --- one cell of k_coef: stencil data (h dQ products counted by the type, 18 FP64 differences by
   //     hand), a = R d, and optionally GENO
@@ -179,14 +181,15 @@ int main() {
   //     then the stage-1 combination (Q*, Acc: 9 per variable; grad*: 2 per sum)
   const long long update_cell = 5 * (3 * (3 + 3 + 3 + 3) + 9) + 15 * 2;
 
-  const long long flux_launch_per_cell = 4 * per_gp;  // 4 Gauss points of the low face, one direction
+  // one direction: the state of the low face and the flux at its 4 Gauss points
+  const long long flux_launch_per_cell = state_face + 4 * (flux_flops + reduce_flops);
   const long long cell_stage_linear = 5 * coef_var + 3 * flux_launch_per_cell + update_cell;
   const long long cell_stage_geno = cell_stage_linear + 5 * geno_var;
   std::printf(
-      "{\"eval_gp\": %lld, \"state_per_gp\": %lld, \"flux_per_gp\": %lld, \"flux_transcendentals\": %lld, "
-      "\"per_gp\": %lld, \"flux_launch_per_cell\": %lld, \"coef_per_var\": %lld, \"geno_per_var\": %lld, "
+      "{\"eval_face\": %lld, \"state_per_face\": %lld, \"flux_per_gp\": %lld, \"flux_transcendentals\": %lld, "
+      "\"reduce_per_gp\": %lld, \"flux_launch_per_cell\": %lld, \"coef_per_var\": %lld, \"geno_per_var\": %lld, "
       "\"update_per_cell\": %lld, \"cell_stage_linear\": %lld, \"cell_stage_geno\": %lld}\n",
-      eval_gp_flops, state_flops, flux_flops, flux_trans, per_gp, flux_launch_per_cell, coef_var,
+      eval_face_flops, state_face, flux_flops, flux_trans, reduce_flops, flux_launch_per_cell, coef_var,
       geno_var, update_cell, cell_stage_linear, cell_stage_geno);
   return 0;
 }

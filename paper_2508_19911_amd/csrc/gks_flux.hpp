@@ -34,23 +34,24 @@ struct Mom {
   T xi2, xi4;
 };
 
+// primitive state of a Maxwellian; var = 1/(2 lam) = p/rho is kept beside lam
 template <class T>
 struct Prim {
-  T rho, U, V, W, lam;
+  T rho, U, V, W, lam, var;
 };
 
 // velocity moments by the Gaussian recursion <x^{k}> = X <x^{k-1}> + (k-1)/(2 lam) <x^{k-2}>
 // (exact for a half range bounded at 0 once k >= 2); HALF = +1 (u > 0), -1 (u < 0) or 0 (full)
 template <int HALF, class T>
 __host__ __device__ __forceinline__ void maxwell_moments(const Prim<T>& p, T Kdof, Mom<T>& m) {
-  const T var = T(0.5) / p.lam;
+  const T var = p.var;
   if constexpr (HALF == 0) {
     m.u[0] = T(1);
     m.u[1] = p.U;
   } else {
     const T sl = dsqrt(p.lam);
-    // e^{-lam U^2} / (2 sqrt(pi lam))
-    const T tail = dexp(-p.lam * p.U * p.U) * (T(0.28209479177387814347) / sl);
+    // e^{-lam U^2} / (2 sqrt(pi lam)) = e^{-lam U^2} sqrt(var / (2 pi))
+    const T tail = dexp(-p.lam * p.U * p.U) * (T(0.39894228040143267794) * dsqrt(var));
     if constexpr (HALF > 0) {
       m.u[0] = T(0.5) * derfc(-sl * p.U);
       m.u[1] = p.U * m.u[0] + tail;
@@ -120,14 +121,16 @@ __host__ __device__ __forceinline__ void smom_acc(const Mom<T>& m, const T s[5],
 }
 
 // Closed-form micro-slope solver: the polynomial a with <a psi> = R for a Maxwellian.
+// ik3 = 1/(K+3).
 template <class T>
-__host__ __device__ __forceinline__ void micro_slope(const Prim<T>& p, T Kdof, const T R[5], T a[5]) {
+__host__ __device__ __forceinline__ void micro_slope(const Prim<T>& p, T Kdof, T ik3, const T R[5],
+                                                     T a[5]) {
   const T Ad = R[1] - p.U * R[0];
   const T Cd = R[2] - p.V * R[0];
   const T Dd = R[3] - p.W * R[0];
-  const T q = p.U * p.U + p.V * p.V + p.W * p.W + (Kdof + T(3)) * (T(0.5) / p.lam);
+  const T q = p.U * p.U + p.V * p.V + p.W * p.W + (Kdof + T(3)) * p.var;
   const T Bd = T(2) * R[4] - q * R[0];
-  a[4] = T(4) * p.lam * p.lam * (Bd - T(2) * (p.U * Ad + p.V * Cd + p.W * Dd)) / (Kdof + T(3));
+  a[4] = T(4) * p.lam * p.lam * (Bd - T(2) * (p.U * Ad + p.V * Cd + p.W * Dd)) * ik3;
   a[1] = T(2) * p.lam * Ad - p.U * a[4];
   a[2] = T(2) * p.lam * Cd - p.V * a[4];
   a[3] = T(2) * p.lam * Dd - p.W * a[4];
@@ -141,13 +144,30 @@ struct FluxParams {
   double tref;       // Sutherland reference temperature (<= 0: constant mu0)
   double prandtl;
   double tau_eps, tau_c;
+  double ik3;        // 1 / (Kdof + 3)
+  double itref;      // 1 / tref (0 when tref <= 0)
 };
+
+inline FluxParams make_flux_params(double gamma, double mu0, double tref, double prandtl,
+                                   double tau_eps, double tau_c) {
+  FluxParams f;
+  f.gamma = gamma;
+  f.Kdof = (5.0 - 3.0 * gamma) / (gamma - 1.0);
+  f.mu0 = mu0;
+  f.tref = tref;
+  f.prandtl = prandtl;
+  f.tau_eps = tau_eps;
+  f.tau_c = tau_c;
+  f.ik3 = 1.0 / (f.Kdof + 3.0);
+  f.itref = tref > 0.0 ? 1.0 / tref : 0.0;
+  return f;
+}
 
 template <class T>
 __host__ __device__ __forceinline__ T viscosity(const FluxParams& P, T Temp) {
   if (P.tref > 0.0) {
-    const T th = Temp / T(P.tref);
-    return T(P.mu0) * T(1.4042) * th * dsqrt(th) / (th + T(0.4042));
+    const T th = Temp * T(P.itref);
+    return T(P.mu0) * T(1.4042) * th * dsqrt(th) * drcp(th + T(0.4042));
   }
   return T(P.mu0);
 }
@@ -159,6 +179,7 @@ template <class T, int NOUT>
 __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt, const double* WL,
                                          const T* DL, const double* WR, const T* DR, T* out) {
   const T K = T(P.Kdof);
+  const T ik3 = T(P.ik3);
   const double gm1 = P.gamma - 1.0;
   // primitive variables in FP64
   double pres[2];
@@ -176,7 +197,8 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
       pr[s].U = data<T>(U);
       pr[s].V = data<T>(V);
       pr[s].W = data<T>(W);
-      pr[s].lam = data<T>(rho / (2.0 * p));
+      pr[s].var = data<T>(p * ir);
+      pr[s].lam = T(0.5) * drcp(pr[s].var);
     }
   }
 
@@ -199,14 +221,14 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
     else
       maxwell_moments<-1>(p, K, mh);
     maxwell_moments<0>(p, K, mf);
-    const T irho = T(1) / p.rho;
+    const T irho = drcp(p.rho);
     T a[3][5];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       T R[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) R[v] = D[d * 5 + v] * irho;
-      micro_slope(p, K, R, a[d]);
+      micro_slope(p, K, ik3, R, a[d]);
     }
     // W0 and its slopes (half-space split)
     T t[5];
@@ -229,7 +251,7 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
       RA[v] = -E[v];
       eul[s][v] = -p.rho * E[v];
     }
-    micro_slope(p, K, RA, A);
+    micro_slope(p, K, ik3, RA, A);
     // the side's pieces of f on its half space
     mvec<1, 0, 0>(mh, t);
 #pragma unroll
@@ -248,12 +270,13 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
   // interface equilibrium g0
   Prim<T> p0;
   p0.rho = W0[0];
-  const T ir0 = T(1) / W0[0];
+  const T ir0 = drcp(W0[0]);
   p0.U = W0[1] * ir0;
   p0.V = W0[2] * ir0;
   p0.W = W0[3] * ir0;
   const T pe = T(gm1) * (W0[4] - T(0.5) * W0[0] * (p0.U * p0.U + p0.V * p0.V + p0.W * p0.W));
-  p0.lam = W0[0] / (T(2) * pe);
+  p0.var = pe * ir0;
+  p0.lam = T(0.5) * drcp(p0.var);
   Mom<T> m0;
   maxwell_moments<0>(p0, K, m0);
   T ab[3][5];
@@ -262,7 +285,7 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
     T R[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) R[v] = dW0[d][v] * ir0;
-    micro_slope(p0, K, R, ab[d]);
+    micro_slope(p0, K, ik3, R, ab[d]);
   }
   T G[6][5];  // rho0 x {<u psi>, <u (ab.u) psi>, <u Ab psi>, <psi>, <(ab.u) psi>, <Ab psi>}
 #pragma unroll
@@ -282,7 +305,7 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
       G[4][v] = p0.rho * E[v];
       G[3][v] = W0[v];
     }
-    micro_slope(p0, K, RA, Ab);
+    micro_slope(p0, K, ik3, RA, Ab);
   }
   {
     T t[5];
@@ -297,20 +320,21 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
   smom_acc<0, 0, 0>(m0, Ab, p0.rho, G[5]);
 
   // collision time (Sec. 4 opening)
-  const double jump = fabs(pres[0] - pres[1]) / (pres[0] + pres[1]);
+  // relative pressure jump |p_l - p_r| / (p_l + p_r): the difference in FP64, the ratio in T
+  const T jump = data<T>(fabs(pres[0] - pres[1])) * drcp(data<T>(pres[0] + pres[1]));
+  const T Dt = T(dt);
   T tau;
   if (P.mu0 > 0.0)
-    tau = viscosity(P, pe / p0.rho) / pe + data<T>(P.tau_c * jump * dt);
+    tau = viscosity(P, p0.var) * drcp(pe) + T(P.tau_c) * jump * Dt;
   else
-    tau = data<T>(P.tau_eps * dt + P.tau_c * jump * dt);
+    tau = (T(P.tau_eps) + T(P.tau_c) * jump) * Dt;
 
   // closed-form coefficients of f^n and f_t^n (time integrals over [0,dt/2] and [0,dt] combined)
-  const T Dt = T(dt);
-  const T om = -dexpm1(-Dt / (T(2) * tau));  // 1 - e^{-dt/(2 tau)}; tau = 0 gives 1
+  const T iDt = T(1.0 / dt);
+  const T om = -dexpm1(T(-0.5) * Dt * drcp(tau));  // 1 - e^{-dt/(2 tau)}; tau = 0 gives 1
   const T e1 = T(1) - om;
-  const T r = tau / Dt;
+  const T r = tau * iDt;
   const T rq = r * om * (T(3) - e1);
-  const T iDt = T(1) / Dt;
   T cn[6], ct[6];
   cn[0] = T(1) - rq;
   cn[1] = T(2) * tau * rq + tau * (e1 * e1 - T(2) * e1 - T(1));
@@ -356,8 +380,8 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
     for (int v = 0; v < 5; ++v)
       Qt[v] = ct[0] * G[3][v] + ct[1] * G[4][v] + ct[2] * G[5][v] + ct[3] * SP[3][v] +
               ct[4] * SP[4][v] + ct[5] * SP[5][v];
-    const double tau0 = P.tau_c * jump * dt;
-    const T w = data<T>(exp(-dt / tau0));  // tau0 = 0 gives 0
+    // w = e^{-dt/tau0}, tau0 = C jump dt; a zero jump gives w = 0
+    const T w = dexp(-drcp(T(P.tau_c) * jump));
     const T w1 = T(1) - w;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {

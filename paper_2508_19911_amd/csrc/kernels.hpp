@@ -39,6 +39,37 @@ __device__ __forceinline__ int neighbour_p(const Grid& g, int cell, int i, int j
   return cell + (wrap_p(k, g.nz) - k) * g.nx * g.ny;
 }
 
+// ============================================================================ coefficient blocks
+// The 34 coefficients of one variable of one cell are stored as chunks of 16 bytes (4 floats or 2
+// doubles).  16 consecutive cells form a block; inside a block, chunk j of variable v of the 16
+// cells is contiguous (256 bytes).  A lane reads a cell's coefficients with 16-byte loads at
+// constant offsets from one address, and 16 lanes reading consecutive cells read 256 contiguous
+// bytes per load.
+template <class T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+
+template <class T>
+struct CoefBlock {
+  static constexpr int PER = 16 / (int)sizeof(T);              // coefficients per chunk
+  static constexpr int NCH = (tab::NB + PER - 1) / PER;         // chunks per variable
+  static constexpr int NBP = NCH * PER;                         // padded coefficients per variable
+  static constexpr long long CHUNK_STRIDE = 16LL * PER;         // elements from chunk j to j + 1
+  // element offset of chunk 0 of variable v of the cell
+  __host__ __device__ static long long base(long long cell, int v) {
+    return ((cell >> 4) * (5 * NCH) + v * NCH) * CHUNK_STRIDE + (cell & 15) * PER;
+  }
+  // elements of the whole array (whole blocks)
+  __host__ __device__ static long long elements(long long N) { return ((N + 15) >> 4) * 5 * NCH * CHUNK_STRIDE; }
+};
+
 // ============================================================================ reconstruction
 // Gather the stencil of one variable and accumulate a = R d column by column; the face-neighbour
 // differences and the cell's own normalised gradient are kept for GENO.
@@ -102,53 +133,92 @@ __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__
     for (int m = 0; m < tab::NB; ++m) a[m] = T(0);
     gather_coefficients<T>(g, Qv, G + v * N, 5 * N, sidx, ld(Qv, (uint32_t)cell), a, dface, g0);
     if (MODE != 0 && geno) geno_blend(dface, g0, a, gp, data<T>(gp.eps + gp.hmax2 * geno_scale(q5, v)));
+    using CB = CoefBlock<T>;
+    using V = typename Vec16<T>::type;
+    T* cb = C + CB::base(cell, v);
 #pragma unroll
-    for (int m = 0; m < tab::NB; ++m) st(C + (v * tab::NB + m) * N, (uint32_t)cell, a[m]);
+    for (int j = 0; j < CB::NCH; ++j) {
+      V x;
+#pragma unroll
+      for (int e = 0; e < CB::PER; ++e) x[e] = j * CB::PER + e < tab::NB ? a[j * CB::PER + e] : T(0);
+      *reinterpret_cast<V*>(cb + j * CB::CHUNK_STRIDE) = x;
+    }
   }
 }
 
 // ============================================================================ CGKS-5th face flux
-// One thread per (face, Gauss point): 4 consecutive lanes hold the 4 Gauss points of the face on the
-// low side of one cell; 64 faces per block.  The 2x2 Gauss average is a 4-lane reduction.
-constexpr int FACES_PER_BLK = BLK / 4;
+// One 64-lane block = the faces on the low side of 16 consecutive cells; 4 consecutive lanes hold
+// the 4 Gauss points of one face.
+//  1. The 10 (variable, side) polynomials of a face are split over its 4 lanes in 3 rounds; a lane
+//     evaluates its polynomial at all 4 Gauss points at once (parity classes) and writes the
+//     point states to LDS.
+//  2. Each lane reads the two states of its own point and evaluates the gas-kinetic flux.
+//  3. The 2x2 Gauss average is a 4-lane reduction; each lane stores a quarter of the 30 outputs.
+constexpr int FLUX_FACES = 16;
+constexpr int FLUX_BLK = 4 * FLUX_FACES;
+
+template <class T>
+struct FluxShared {
+  double W[FLUX_FACES][4][10];   // [face][point][side * 5 + face-frame variable]: conservative value
+  T D[FLUX_FACES][4][10][3];     // face-frame derivatives, physical units
+};
 
 template <class T, int DIR>
-__global__ __launch_bounds__(BLK) void k_flux5(Grid g, const double* __restrict__ Q,
-                                               const T* __restrict__ C, T* __restrict__ F,
-                                               FluxParams fp, double dt) {
+__global__ __launch_bounds__(FLUX_BLK) void k_flux5(Grid g, const double* __restrict__ Q,
+                                                    const T* __restrict__ C, T* __restrict__ F,
+                                                    FluxParams fp, double dt) {
+  __shared__ FluxShared<T> sh;
+  constexpr int FP = 2 * DIR + 1;  // tables of the + face of the axis
+  using CB = CoefBlock<T>;
+  using V = typename Vec16<T>::type;
   const int kgp = threadIdx.x & 3;
-  int cell = blockIdx.x * FACES_PER_BLK + (threadIdx.x >> 2);
+  const int fl = threadIdx.x >> 2;
+  int cell = blockIdx.x * FLUX_FACES + fl;
   const bool active = cell < g.N;
-  if (!active) cell = g.N - 1;  // keep the lane in the reduction; its result is not stored
+  if (!active) cell = (int)g.N - 1;  // keep the lane in the reduction; its result is not stored
   int i, j, k;
   cell_ijk(g, cell, i, j, k);
   const int left = neighbour_m<DIR>(g, cell, i, j, k);
   const long long N = g.N;
-  // tangential signs of the Gauss points (-,-), (-,+), (+,-), (+,+)
-  static_assert(tab::GP_SIGN[0][0] == -1 && tab::GP_SIGN[1][1] == 1 && tab::GP_SIGN[2][0] == 1,
-                "Gauss point order");
-  const T s1 = T(kgp < 2 ? -1 : 1);
-  const T s2 = T((kgp & 1) ? 1 : -1);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int vs = 4 * r + kgp;  // side * 5 + face-frame variable
+    if (r < 2 || vs < 10) {
+      const int side = vs >= 5 ? 1 : 0;  // 0: the low cell (its + face), 1: this cell (its - face)
+      const int vf = vs - 5 * side;
+      const int vg = (vf >= 1 && vf <= 3) ? 1 + (DIR + vf - 1) % 3 : vf;
+      const int src = side ? cell : left;
+      const T* cb = C + CB::base(src, vg);
+      T a[CB::NBP];
+#pragma unroll
+      for (int c = 0; c < CB::NCH; ++c) {
+        const V x = *reinterpret_cast<const V*>(cb + c * CB::CHUNK_STRIDE);
+#pragma unroll
+        for (int e = 0; e < CB::PER; ++e) a[c * CB::PER + e] = x[e];
+      }
+      T val[4], der[4][3];
+      eval_face<FP>(a, side ? T(-1) : T(1), val, der);
+      const double q0 = ld(Q + vg * N, (uint32_t)src);
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        sh.W[fl][p][vs] = q0 + double(val[p]);
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) sh.D[fl][p][vs][dd] = der[p][perm(DIR, dd)] * T(g.ih[perm(DIR, dd)]);
+      }
+    }
+  }
+  __syncthreads();
   double WL[5], WR[5];
   T DL[15], DR[15];
 #pragma unroll
   for (int vf = 0; vf < 5; ++vf) {
-    const int vg = (vf >= 1 && vf <= 3) ? 1 + perm(DIR, vf - 1) : vf;
-    T a[tab::NB], val, der[3];
+    WL[vf] = sh.W[fl][kgp][vf];
+    WR[vf] = sh.W[fl][kgp][5 + vf];
 #pragma unroll
-    for (int m = 0; m < tab::NB; ++m) a[m] = ld(C + (vg * tab::NB + m) * N, (uint32_t)left);
-    eval_gp<2 * DIR + 1>(a, s1, s2, val, der);
-    WL[vf] = ld(Q + vg * N, (uint32_t)left) + double(val);
-#pragma unroll
-    for (int dd = 0; dd < 3; ++dd) DL[dd * 5 + vf] = der[perm(DIR, dd)] * T(g.ih[perm(DIR, dd)]);
-#pragma unroll
-    for (int m = 0; m < tab::NB; ++m) a[m] = ld(C + (vg * tab::NB + m) * N, (uint32_t)cell);
-    eval_gp<2 * DIR>(a, s1, s2, val, der);
-    WR[vf] = ld(Q + vg * N, (uint32_t)cell) + double(val);
-#pragma unroll
-    for (int dd = 0; dd < 3; ++dd) DR[dd * 5 + vf] = der[perm(DIR, dd)] * T(g.ih[perm(DIR, dd)]);
-    // one variable at a time: 68 coefficients live, not 340
-    __builtin_amdgcn_sched_barrier(0);
+    for (int dd = 0; dd < 3; ++dd) {
+      DL[dd * 5 + vf] = sh.D[fl][kgp][vf][dd];
+      DR[dd * 5 + vf] = sh.D[fl][kgp][5 + vf][dd];
+    }
   }
   T out[30];
   gks_flux<T, 30>(fp, dt, WL, DL, WR, DR, out);

@@ -173,4 +173,72 @@ __host__ __device__ __forceinline__ void eval_gp(const T* a, T s1, T s2, T& val,
   eval_gp_impl<F>(a, s1, s2, val, der, std::make_integer_sequence<int, tab::NB>{});
 }
 
+// ---- all four Gauss points of a face, either side -------------------------------------------------------
+// Evaluated at the (+,+) point of face F = 2e+1 (normal coordinate +1/2), a basis function's value
+// changes sign with the normal coordinate when its normal exponent is odd and with a tangential
+// sign when that exponent is odd; the zero-mean shift is nonzero only for all-even exponents.  So
+// eight parity-class sums give the values at the four points of the + face (sn = +1) and, with
+// sn = -1, of the - face of the same axis.  Class bits: 1 = t1 odd, 2 = t2 odd, 4 = normal odd.
+template <int F, int M, int AX>
+constexpr int parity_class8() {
+  constexpr int e = F / 2, t1 = (e + 1) % 3, t2 = (e + 2) % 3;
+  int d[3] = {tab::BD[M][0], tab::BD[M][1], tab::BD[M][2]};
+  if (AX >= 0) d[AX] -= 1;
+  return (d[t1] & 1) | ((d[t2] & 1) << 1) | ((d[e] & 1) << 2);
+}
+
+// the four point values from the eight class sums, in the table's point order (-,-), (-,+), (+,-), (+,+)
+template <class T>
+__host__ __device__ __forceinline__ void gp_combine(const T v[8], T sn, T out[4]) {
+  T u[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) u[t] = dfma(sn, v[4 + t], v[t]);
+  const T A = u[0] + u[3], B = u[1] + u[2], C = u[0] - u[3], D = u[1] - u[2];
+  out[0] = A - B;
+  out[1] = C - D;
+  out[2] = C + D;
+  out[3] = A + B;
+}
+
+template <int F, class T, int... M>
+__host__ __device__ __forceinline__ void eval_face_impl(const T* a, T sn, T* val, T (*der)[3],
+                                                        std::integer_sequence<int, M...>) {
+  T v[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+  ((v[parity_class8<F, M, -1>()] = dfma(T(tab::PV[F][3][M]), a[M], v[parity_class8<F, M, -1>()])), ...);
+  gp_combine(v, sn, val);
+  T w[3][8];
+#pragma unroll
+  for (int x = 0; x < 3; ++x)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) w[x][c] = T(0);
+  ((tab::BD[M][0] > 0 ? (void)(w[0][parity_class8<F, M, 0>()] =
+                                   dfma(T(tab::PD[F][3][0][M]), a[M], w[0][parity_class8<F, M, 0>()]))
+                      : (void)0), ...);
+  ((tab::BD[M][1] > 0 ? (void)(w[1][parity_class8<F, M, 1>()] =
+                                   dfma(T(tab::PD[F][3][1][M]), a[M], w[1][parity_class8<F, M, 1>()]))
+                      : (void)0), ...);
+  ((tab::BD[M][2] > 0 ? (void)(w[2][parity_class8<F, M, 2>()] =
+                                   dfma(T(tab::PD[F][3][2][M]), a[M], w[2][parity_class8<F, M, 2>()]))
+                      : (void)0), ...);
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    T o[4];
+    gp_combine(w[x], sn, o);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) der[g][x] = o[g];
+  }
+}
+
+// value and the three normalised derivatives of sum_m a_m p_m at the four Gauss points of the face
+// of axis e = F/2 on the + side (sn = +1) or the - side (sn = -1); F must be the + face
+template <int F, class T>
+__host__ __device__ __forceinline__ void eval_face(const T* a, T sn, T val[4], T der[4][3]) {
+  static_assert(F % 2 == 1, "tables of the + face");
+  static_assert(tab::GP_SIGN[0][0] == -1 && tab::GP_SIGN[0][1] == -1 && tab::GP_SIGN[1][0] == -1 &&
+                    tab::GP_SIGN[1][1] == 1 && tab::GP_SIGN[2][0] == 1 && tab::GP_SIGN[2][1] == -1 &&
+                    tab::GP_SIGN[3][0] == 1 && tab::GP_SIGN[3][1] == 1,
+                "Gauss point order");
+  eval_face_impl<F>(a, sn, val, der, std::make_integer_sequence<int, tab::NB>{});
+}
+
 }  // namespace cgks
