@@ -32,6 +32,23 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector peaks (FP32 packed-math figure)
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per k_flux5<float> launch on the 128^3 grid (mean over the three directions, read +
+# write), from two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE) scaled by a 1 GiB copy
+# kernel: profiles/flux_tgv128_hbm_counters.md.  Valid only for the kernel sources they were taken
+# on; any change to those sources makes the reported traffic null until the counters are retaken.
+FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 2.1517e9,
+                "sources_sha256": "9d8494d6a74f4d91d1e5187c5188cd4c1af0cbb4d9434d40ff652650ecdec8b9"}
+KERNEL_SOURCES = ["common.hpp", "gks_flux.hpp", "recon.hpp", "recon_tables.hpp", "kernels.hpp"]
+
+
+def kernel_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2508_19911_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
 
 def load_flops():
     with open(os.path.join(ROOT, "paper_2508_19911_amd", "flops.json")) as f:
@@ -77,7 +94,20 @@ def run_variant(case, precision, steps, warmup, timing, indicator=None):
     return {"seconds": t1 - t0, "steps": done, "t": t_now, "kernels": kt, "diag": diag, "vel": vel}
 
 
-def cpu_baseline(n=48):
+def copy_calibration(nbytes=1 << 30):
+    """One plain device-to-device copy of nbytes (a kernel of known HBM traffic: nbytes read, nbytes
+    written), so that a hardware-counter pass can scale FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    torch.cuda.empty_cache()
+
+
+def cpu_baseline(n=56):
     """The FP64 oracle (OpenMP over the host's cores) on one CGKS-5th GENO step of the same flow at n^3."""
     import oracle
     from paper_2508_19911_amd import inputs
@@ -102,6 +132,8 @@ def main():
     ap.add_argument("--grid", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the sweep is not sharded across GPUs.",
@@ -116,6 +148,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     flops = load_flops()
     indicator = load_indicator()
+    if args.copy_calibration:
+        copy_calibration()
     n = args.grid
     base = inputs.tgv_case(n, ma=0.1, re=1600.0, prandtl=0.72)
     N = base.N
@@ -132,8 +166,11 @@ def main():
     flux_ms = kms / max(kc, 1)
     per_cell = flops["flux_launch_per_cell"]
     achieved = per_cell * N / (flux_ms * 1e-3) / 1e12
+    traffic = None
+    if n == FLUX_TRAFFIC["grid"] and kernel_digest() == FLUX_TRAFFIC["sources_sha256"]:
+        traffic = FLUX_TRAFFIC["bytes_per_launch"]
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": None, "kernel": "k_flux5<float>",
+            "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": traffic, "kernel": "k_flux5<float>",
             "flops_per_launch": per_cell * N, "mean_launch_ms": round(flux_ms, 4)}
     kernels = {k: {"launches": c, "ms": round(m, 3)} for k, (c, m) in head["kernels"].items()}
 
