@@ -43,7 +43,8 @@ enum {
 };
 enum { CGKS_SCHEME_CGKS5 = 0, CGKS_SCHEME_GKS2 = 1 };
 /* CGKS5: LINEAR = P^4 everywhere, NONLINEAR = GENO everywhere, LEARNED = GENO where the troubled-cell
- * network flags the cell.  GKS2: LINEAR = unlimited P^1, NONLINEAR = Venkatakrishnan limiter. */
+ * network flags the cell (evaluated once per time step on Q^n; both stages use those flags).
+ * GKS2: LINEAR = unlimited P^1, NONLINEAR = Venkatakrishnan limiter. */
 enum { CGKS_RECON_LINEAR = 0, CGKS_RECON_NONLINEAR = 1, CGKS_RECON_LEARNED = 2 };
 /* FP64: every step in double.  FP32_BULK: reconstruction, flux and gradient state in float;
  * cell averages, their stage accumulations, Gauss-point states and cons->prim in double. */
@@ -75,7 +76,7 @@ typedef struct {
   double Ek, epsS, epsD, epsT;
   double mass, momx, momy, momz, energy; /* sums of Q |Omega_i| */
   double rho_min, p_min;
-  double flagged_fraction;               /* cells that ran GENO in the last stage (1 unless LEARNED) */
+  double flagged_fraction;               /* cells that ran the nonlinear blend in the last stage */
   double t;
   double step;
   double reserved[2];
@@ -112,15 +113,19 @@ int cgks_step_fixed(void* ctx, int nsteps, double dt);
 int cgks_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double* sqt);
 
 int cgks_diagnostics(void* ctx, double rho0, double u0, cgks_diag* out);
-/* GENO flags (1 byte per cell) used by the last stage. */
+/* Flags (1 byte per cell): the cells on which the nonlinear blend ran in the last stage (GENO, or
+ * the limiter of GKS2): 0 everywhere for LINEAR, 1 for NONLINEAR, the network's decision for LEARNED. */
 int cgks_get_flags(void* ctx, unsigned char* flags);
 
 /* ---- troubled-cell network (the learned form of the indicator) -------------------------------------
- * 64 inputs (54 used) -> 32 -> 32 -> 32 -> 1, ReLU, logit output; params[4225] float:
+ * 64 inputs (59 used) -> 32 -> 32 -> 32 -> 1, ReLU, logit output; params[4225] float:
  * W1[32][64], b1[32], W2[32][32], b2[32], W3[32][32], b3[32], w4[32], b4.  Hidden layers run on BF16
  * matrix cores with FP32 accumulation.  Inputs: for rho and rho E, along each axis, the values of the
  * cells i-2..i+2 minus the centre value and h dQ/dx of the same five cells, over
- * s = max|difference| + max|h dQ| + 1e-12 |Q_i|. */
+ * s = max|difference| + max|h dQ| + 1e-12 |Q_i| (inputs 0..53); for each of the 5 conservative
+ * variables, log10 of the largest such difference or h dQ over h_max sqrt(S_v), S_v = rho^2,
+ * 2 rho rhoE (momenta), (rhoE)^2 of the cell (inputs 54..58, clipped below at -12): the variation
+ * against the smoothness floor of the GENO weights, which the label depends on. */
 int cgks_indicator_set(void* ctx, const float* params, size_t n, double logit_threshold);
 int cgks_indicator_get(void* ctx, float* params, size_t n);
 /* Features of every cell of the current state (N x 64 float, host). */

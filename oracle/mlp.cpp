@@ -3,7 +3,7 @@
  * binary cross-entropy.  TEST INFRASTRUCTURE ONLY.
  *
  * The indicator is not part of the paper; it is the learned form asked for alongside the
- * method (reading R17): 64 inputs (54 used) -> 32 -> 32 -> 32 -> 1, ReLU hidden layers, a
+ * method (reading R17): 64 inputs (59 used) -> 32 -> 32 -> 32 -> 1, ReLU hidden layers, a
  * logit output.  Parameter layout (float): W1[32][64], b1[32], W2[32][32], b2[32], W3[32][32],
  * b3[32], w4[32], b4.  With bf16 emulation on, the inputs of the three hidden layers (x, h1,
  * h2) and their weights are rounded to bfloat16 (nearest even), matching BF16 matrix-core

@@ -44,11 +44,30 @@ static inline long cell_index(const Ctx& c, long i, long j, long k) {
 
 // Features of the troubled-cell indicator (reading R17): for rho and rho E, along each axis,
 // the values of the cells i-2..i+2 minus the centre value (centre dropped) and h_d dQ/dx_d of
-// the same five cells, scaled by s = max|difference| + max|h dQ| + 1e-12 |Q_i|; zero padded.
+// the same five cells, scaled by s = max|difference| + max|h dQ| + 1e-12 |Q_i| (features 0..53).
+// Those are scale-free, but the GENO label compares the variation with the smoothness floor
+// h_max^2 S_v, so features 54..58 give, for each conservative variable v, log10 of the largest
+// difference or h dQ on the same lines over h_max sqrt(S_v) (clipped below at -12); zero padded.
 static void cell_features(const Ctx& c, const double* Q, const double* G, long i, long j, long k,
                           double f[64]) {
   const long N = c.N;
   for (int n = 0; n < 64; ++n) f[n] = 0.0;
+  {
+    const long c0 = cell_index(c, i, j, k);
+    double q5[5];
+    for (int v = 0; v < 5; ++v) q5[v] = Q[v * N + c0];
+    const double hmax = std::fmax(c.h[0], std::fmax(c.h[1], c.h[2]));
+    for (int v = 0; v < 5; ++v) {
+      double mx = 0.0;
+      for (int d = 0; d < 3; ++d)
+        for (int o = -2; o <= 2; ++o) {
+          const long ci = cell_index(c, i + (d == 0 ? o : 0), j + (d == 1 ? o : 0), k + (d == 2 ? o : 0));
+          mx = std::fmax(mx, std::fabs(Q[v * N + ci] - q5[v]));
+          mx = std::fmax(mx, std::fabs(c.h[d] * G[(5 * d + v) * N + ci]));
+        }
+      f[54 + v] = std::fmax(std::log10(mx / (hmax * std::sqrt(geno_scale(q5, v)))), -12.0);
+    }
+  }
   const int vars[2] = {0, 4};
   const long c0 = cell_index(c, i, j, k);
   for (int vi = 0; vi < 2; ++vi) {
@@ -80,7 +99,8 @@ static void cell_features(const Ctx& c, const double* Q, const double* G, long i
 
 static void compute_flags(Ctx& c, const double* Q, const double* G) {
   const cgkso_params& P = c.P;
-  c.flags.assign(c.N, 1);
+  // flags = the cells on which the nonlinear blend (GENO, or the limiter of GKS-2nd) runs
+  c.flags.assign(c.N, P.recon == CGKSO_RECON_LINEAR ? 0 : 1);
   if (P.recon != CGKSO_RECON_LEARNED) return;
   std::vector<float> X(c.N * 64);
 #pragma omp parallel for collapse(2)
@@ -101,14 +121,16 @@ static void compute_flags(Ctx& c, const double* Q, const double* G) {
 // x-faces (x,y,z), y-faces (y,z,x), z-faces (z,x,y).
 static inline int perm(int d, int k) { return (d + k) % 3; }
 
-// One stage of CGKS-5th on (Q, G) with step size dt.
+// One stage of CGKS-5th on (Q, G) with step size dt.  With the learned indicator the flags are
+// evaluated on the stage's input when new_flags is set; the second stage of a step keeps those of
+// the first (the indicator is evaluated once per time step, on Q^n).
 static void stage_cgks5(Ctx& c, const double* Q, const double* G, double dt, double* L, double* Lt,
-                        double* sqn, double* sqt) {
+                        double* sqn, double* sqt, bool new_flags = true) {
   const cgkso_params& P = c.P;
   const long N = c.N;
   int off[NSTEN][3];
   stencil_offsets(off);
-  compute_flags(c, Q, G);
+  if (new_flags) compute_flags(c, Q, G);
 
   // reconstructed values and gradients at the 24 face Gauss points of every cell
   std::vector<double> rec(N * 480);
@@ -309,7 +331,7 @@ static void advance(Ctx& c, double dt) {
     std::vector<double> Qs(5 * N), Gs(15 * N);
     for (long n = 0; n < 5 * N; ++n) Qs[n] = c.Q[n] + 0.5 * dt * L0[n] + 0.125 * dt * dt * Lt0[n];
     for (long n = 0; n < 15 * N; ++n) Gs[n] = sqn0[n] + 0.5 * dt * sqt0[n];
-    stage_cgks5(c, Qs.data(), Gs.data(), dt, nullptr, Lt1.data(), nullptr, sqt1.data());
+    stage_cgks5(c, Qs.data(), Gs.data(), dt, nullptr, Lt1.data(), nullptr, sqt1.data(), false);
     for (long n = 0; n < 5 * N; ++n)
       c.Q[n] += dt * L0[n] + dt * dt / 6.0 * (Lt0[n] + 2.0 * Lt1[n]);
     for (long n = 0; n < 15 * N; ++n) c.G[n] = sqn0[n] + dt * sqt1[n];
@@ -337,7 +359,7 @@ int cgkso_create(const cgkso_params* p, void** out) {
   c->h[2] = p->lz / p->nz;
   c->Q.assign(5 * c->N, 0.0);
   c->G.assign(15 * c->N, 0.0);
-  c->flags.assign(c->N, 1);
+  c->flags.assign(c->N, p->recon == CGKSO_RECON_LINEAR ? 0 : 1);
   *out = c;
   return CGKSO_OK;
 }

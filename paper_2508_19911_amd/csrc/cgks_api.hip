@@ -173,10 +173,11 @@ int launch_coef(Ctx& c, const double* Q, const T* G) {
   return CGKS_OK;
 }
 
-// one CGKS-5th stage on (Q, G); STAGE 0 debug, 1 first, 2 second
+// one CGKS-5th stage on (Q, G); STAGE 0 debug, 1 first, 2 second.  The learned indicator runs once
+// per time step, on the first stage's input; the second stage keeps its flags.
 template <class T, int STAGE>
 int stage5(Ctx& c, const double* Q, const T* G, double dt) {
-  int rc = run_flags<T>(c, Q, G);
+  int rc = STAGE == 2 ? CGKS_OK : run_flags<T>(c, Q, G);
   if (rc) return rc;
   rc = launch_coef<T>(c, Q, G);
   if (rc) return rc;
@@ -321,8 +322,9 @@ int cgks_create(const cgks_params* p, void* ws, size_t bytes, void* stream, void
   const double hh = std::cbrt(c->g.h[0] * c->g.h[1] * c->g.h[2]);
   c->vk_eps2 = std::pow(p->vk_k * hh, 3.0);
   c->nblk = (int)((c->g.N + BLK - 1) / BLK);
-  // every cell runs GENO unless the indicator says otherwise
-  hipError_t e = hipMemsetAsync(c->ws + L.flags, 1, c->g.N, c->stream);
+  // flags = the cells on which the nonlinear blend (GENO, or the GKS-2nd limiter) runs: none for
+  // LINEAR, all for NONLINEAR; LEARNED overwrites them before every stage
+  hipError_t e = hipMemsetAsync(c->ws + L.flags, p->recon == CGKS_RECON_LINEAR ? 0 : 1, c->g.N, c->stream);
   if (e != hipSuccess) {
     delete c;
     return dev_error("hipMemsetAsync", e);

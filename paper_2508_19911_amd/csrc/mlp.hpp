@@ -2,9 +2,11 @@
 //
 // The learned form of the GENO switch: a cell whose logit exceeds the threshold runs the full
 // nonlinear GENO reconstruction, the others take the linear P^4 (both from arXiv 2508.19911,
-// Sec. 3.2).  Network: 64 inputs (54 used) -> 32 -> 32 -> 32 -> 1, ReLU, logit output.
+// Sec. 3.2).  Network: 64 inputs (59 used) -> 32 -> 32 -> 32 -> 1, ReLU, logit output.
 //   * inputs: for rho and rho E, along x, y, z: Q(i+o) - Q(i) for o = -2,-1,1,2 and h dQ/dx of the
-//     cells o = -2..2, divided by s = max|difference| + max|h dQ| + 1e-12 |Q(i)|;
+//     cells o = -2..2, divided by s = max|difference| + max|h dQ| + 1e-12 |Q(i)|; then for each of
+//     the 5 variables log10(max |difference or h dQ| on those lines / (h_max sqrt(S_v))), the
+//     variation against the GENO smoothness floor (clipped below at -12);
 //   * forward: hidden layers on v_mfma_f32_16x16x16_bf16 (bf16 inputs and weights, fp32
 //     accumulation), bias + ReLU in fp32, h1 and h2 rounded to bf16 for the next layer, h3 kept in
 //     fp32 for the final dot product with w4;
@@ -85,17 +87,42 @@ __device__ __forceinline__ void cell_features(const Grid& g, const double* __res
         mxg = fmax(mxg, fabs(gg));
       }
     }
-    const double s = mxd + mxg + 1e-12 * fabs(q0);
+    const double is = 1.0 / (mxd + mxg + 1e-12 * fabs(q0));
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) f[vi * 27 + d * 9 + m] = float(dv[d][m] / s);
+      for (int m = 0; m < 4; ++m) f[vi * 27 + d * 9 + m] = float(dv[d][m] * is);
 #pragma unroll
-      for (int m = 0; m < 5; ++m) f[vi * 27 + d * 9 + 4 + m] = float(gv[d][m] / s);
+      for (int m = 0; m < 5; ++m) f[vi * 27 + d * 9 + 4 + m] = float(gv[d][m] * is);
+    }
+  }
+  // features 54..58: per conservative variable, log10 of the largest difference or h dQ on the same
+  // lines over h_max sqrt(S_v), S_v the variable's GENO scale (clipped below at -12)
+  {
+    double q5[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q5[v] = Q[v * N + cell];
+    const double hmax = fmax(g.h[0], fmax(g.h[1], g.h[2]));
+#pragma unroll 1
+    for (int v = 0; v < 5; ++v) {
+      double mx = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int o = -2; o <= 2; ++o) {
+          const int ii = d == 0 ? wrap_o(i, o, g.nx) : i;
+          const int jj = d == 1 ? wrap_o(j, o, g.ny) : j;
+          const int kk = d == 2 ? wrap_o(k, o, g.nz) : k;
+          const int c = (kk * g.ny + jj) * g.nx + ii;
+          mx = fmax(mx, fabs(Q[v * N + c] - q5[v]));
+          mx = fmax(mx, fabs(g.h[d] * double(G[(d * 5 + v) * N + c])));
+        }
+      // the ratio in FP64, its logarithm in FP32 (a feature needs no more)
+      f[54 + v] = fmaxf(log10f(float(mx / (hmax * sqrt(geno_scale(q5, v))))), -12.0f);
     }
   }
 #pragma unroll
-  for (int n = 54; n < 64; ++n) f[n] = 0.0f;
+  for (int n = 59; n < 64; ++n) f[n] = 0.0f;
 }
 
 template <class T>
@@ -158,9 +185,12 @@ int launch_labels(const Grid& g, const double* Q, const T* G, const GenoParams& 
 // ---------------------------------------------------------------------------- forward (one wave)
 // xs: 64 x 64 bf16 (row = sample) in LDS; h1: 64 x 32 bf16; w: bf16 W1|W2|W3 in LDS.
 // On return, z[mt][nt] holds layer-3 pre-activations; z1/z2 (optional) keep layers 1 and 2.
-struct WaveLDS {
-  uint16_t x[64 * 64];
-  uint16_t h1[64 * 32];
+// Inference staging of one wave: rows padded by 4 bf16 (8 bytes), so the 16 rows an MFMA operand load
+// touches fall on different LDS banks, and every 4-element operand is one aligned 8-byte access.
+constexpr int XS = 64 + 4, HS = 32 + 4;
+struct alignas(16) WaveLDS {
+  uint16_t x[64 * XS];   // features, then the second hidden layer (row stride HS)
+  uint16_t h1[64 * HS];
 };
 
 __device__ __forceinline__ f32x4 mfma_bf16(bf16x4 a, bf16x4 b, f32x4 c) {
@@ -170,11 +200,13 @@ __device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// One dense layer Y = X W^T + b on the wave's 64 rows: X [64][K] bf16 (row stride K), W [32][K]
-// bf16 (row stride K), result tile (mt, nt) in acc[mt][nt] (lane: rows 4(l/16)+r, column l%16).
-template <int K>
+// One dense layer Y = X W^T + b on the wave's 64 rows: X [64][K] bf16 (row stride XR), W [32][K]
+// bf16 (row stride WR), result tile (mt, nt) in acc[mt][nt] (lane: rows 4(l/16)+r, column l%16).
+// Both strides keep every 4-element operand 8-byte aligned.
+template <int K, int XR = K, int WR = K>
 __device__ __forceinline__ void dense_bf16(const uint16_t* X, const uint16_t* W, const float* bias,
                                            f32x4 acc[4][2]) {
+  static_assert(XR % 4 == 0 && WR % 4 == 0, "8-byte operand rows");
   const int l = threadIdx.x & 63;
   const int r16 = l & 15, q = l >> 4;
 #pragma unroll
@@ -188,21 +220,19 @@ __device__ __forceinline__ void dense_bf16(const uint16_t* X, const uint16_t* W,
   for (int kt = 0; kt < K / 16; ++kt) {
     bf16x4 bw[2];
 #pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-      const uint16_t* p = W + (nt * 16 + r16) * K + kt * 16 + 4 * q;
-      bw[nt] = bf16x4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-    }
+    for (int nt = 0; nt < 2; ++nt)
+      bw[nt] = *reinterpret_cast<const bf16x4*>(W + (nt * 16 + r16) * WR + kt * 16 + 4 * q);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
-      const uint16_t* p = X + (mt * 16 + r16) * K + kt * 16 + 4 * q;
-      const bf16x4 a = bf16x4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+      const bf16x4 a = *reinterpret_cast<const bf16x4*>(X + (mt * 16 + r16) * XR + kt * 16 + 4 * q);
 #pragma unroll
       for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = mfma_bf16(a, bw[nt], acc[mt][nt]);
     }
   }
 }
 
-// ReLU of a layer result, rounded to bf16, stored row-major [64][32] in LDS
+// ReLU of a layer result, rounded to bf16, stored row-major [64][32] (row stride HR) in LDS
+template <int HR = 32>
 __device__ __forceinline__ void store_relu_bf16(const f32x4 acc[4][2], uint16_t* H) {
   const int l = threadIdx.x & 63;
   const int r16 = l & 15, q = l >> 4;
@@ -213,7 +243,7 @@ __device__ __forceinline__ void store_relu_bf16(const f32x4 acc[4][2], uint16_t*
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float z = acc[mt][nt][r];
-        H[(mt * 16 + 4 * q + r) * 32 + nt * 16 + r16] = f2bf(z > 0.0f ? z : 0.0f);
+        H[(mt * 16 + 4 * q + r) * HR + nt * 16 + r16] = f2bf(z > 0.0f ? z : 0.0f);
       }
 }
 
@@ -247,9 +277,15 @@ __global__ __launch_bounds__(256) void k_infer(Grid g, const double* __restrict_
                                                unsigned char* __restrict__ flags,
                                                float* __restrict__ logits, float thr) {
   __shared__ WaveLDS wl[4];
-  __shared__ uint16_t wsh[32 * 64 + 2 * 32 * 32];
+  // bf16 weights, rows padded like the activations: W1 [32][XS], W2 and W3 [32][HS]
+  constexpr int OWS2 = 32 * XS, OWS3 = OWS2 + 32 * HS, NWS = OWS3 + 32 * HS;
+  __shared__ alignas(16) uint16_t wsh[NWS];
   __shared__ float bsh[3 * 32 + 32 + 1];
-  for (int n = threadIdx.x; n < 32 * 64 + 2 * 32 * 32; n += 256) wsh[n] = f2bf(params[n < 2048 ? n : (n < 3072 ? OW2 + n - 2048 : OW3 + n - 3072)]);
+  for (int n = threadIdx.x; n < 32 * 64; n += 256) wsh[(n >> 6) * XS + (n & 63)] = f2bf(params[OW1 + n]);
+  for (int n = threadIdx.x; n < 32 * 32; n += 256) {
+    wsh[OWS2 + (n >> 5) * HS + (n & 31)] = f2bf(params[OW2 + n]);
+    wsh[OWS3 + (n >> 5) * HS + (n & 31)] = f2bf(params[OW3 + n]);
+  }
   for (int n = threadIdx.x; n < 32; n += 256) {
     bsh[n] = params[OB1 + n];
     bsh[32 + n] = params[OB2 + n];
@@ -269,17 +305,19 @@ __global__ __launch_bounds__(256) void k_infer(Grid g, const double* __restrict_
 #pragma unroll
       for (int n = 0; n < 64; ++n) f[n] = 0.0f;
 #pragma unroll
-    for (int n = 0; n < 64; ++n) wl[w].x[l * 64 + n] = f2bf(f[n]);
+    for (int n = 0; n < 64; n += 4)
+      *reinterpret_cast<bf16x4*>(wl[w].x + l * XS + n) =
+          bf16x4{(short)f2bf(f[n]), (short)f2bf(f[n + 1]), (short)f2bf(f[n + 2]), (short)f2bf(f[n + 3])};
   }
   __syncthreads();
   f32x4 acc[4][2];
-  dense_bf16<64>(wl[w].x, wsh, bsh, acc);
-  store_relu_bf16(acc, wl[w].h1);
+  dense_bf16<64, XS, XS>(wl[w].x, wsh, bsh, acc);
+  store_relu_bf16<HS>(acc, wl[w].h1);
   __syncthreads();
-  dense_bf16<32>(wl[w].h1, wsh + 2048, bsh + 32, acc);
-  store_relu_bf16(acc, wl[w].x);  // h2 reuses the input rows
+  dense_bf16<32, HS, HS>(wl[w].h1, wsh + OWS2, bsh + 32, acc);
+  store_relu_bf16<HS>(acc, wl[w].x);  // h2 reuses the input rows
   __syncthreads();
-  dense_bf16<32>(wl[w].x, wsh + 3072, bsh + 64, acc);
+  dense_bf16<32, HS, HS>(wl[w].x, wsh + OWS3, bsh + 64, acc);
   float z[4][4];
   logits_from_z3(acc, bsh + 96, bsh[128], z);
   if ((l & 15) == 0) {
@@ -305,7 +343,7 @@ int launch_infer(const Grid& g, const double* Q, const T* G, const float* params
 }
 
 // ---------------------------------------------------------------------------- training step
-struct TrainLDS {
+struct alignas(16) TrainLDS {
   uint16_t x[64 * 64];
   float z1[64 * 32];
   uint16_t h1[64 * 32];

@@ -89,10 +89,39 @@ def test_features_uniform_and_smooth():
     q, g = inputs.uniform_state(case)
     o.set_state(q, g)
     f = o.features()
-    assert f.shape == (case.N, 64) and np.all(f == 0)
+    assert f.shape == (case.N, 64) and np.all(f[:, :54] == 0) and np.all(f[:, 59:] == 0)
+    assert np.all(f[:, 54:59] == -12.0)  # no variation at all: the clip
     q, g = inputs.tgv_state(case)
     o.set_state(q, g)
     f = o.features()
-    assert np.all(np.abs(f) <= 1.0 + 1e-6)
-    assert np.all(f[:, 54:] == 0)
+    assert np.all(np.abs(f[:, :54]) <= 1.0 + 1e-6)
+    assert np.all(f[:, 59:] == 0)
     assert np.abs(f[:, :54]).max() > 0.1
+    # every feature is unchanged when the whole state is scaled (rho, rho U, rho E all by 3)
+    o.set_state(3.0 * q, 3.0 * g)
+    f3 = o.features()
+    assert np.allclose(f3, f, rtol=0, atol=2e-6)
+
+
+def test_scale_features_single_cell_bump():
+    """A density bump delta in one cell of a uniform gas at rest (pressure uniform, zero gradients):
+    only the density scale feature moves, and only for the cells whose 5-cell axis lines reach the
+    bump: log10(delta / (h_max rho_i)); every other cell and variable sits at the clip, -12."""
+    n = 8
+    case = inputs.tgv_case(n, ma=0.3).with_(nx=n, ny=n, nz=n, lx=1.6, ly=1.2, lz=0.8)
+    q, g = inputs.uniform_state(case, rho=1.0, u=(0.0, 0.0, 0.0), p=0.7)
+    delta = 0.05
+    bump = (3 * n + 4) * n + 5  # (i, j, k) = (5, 4, 3)
+    q[0, bump] += delta
+    o = oracle.Oracle(oracle.params_from_config(case))
+    o.set_state(q, g)
+    f = o.features()
+    hmax = 1.6 / n
+    for c in range(case.N):
+        i, j, k = c % n, (c // n) % n, c // (n * n)
+        d = [abs(i - 5), abs(j - 4), abs(k - 3)]
+        on_line = sorted(d)[:2] == [0, 0] and max(d) <= 2
+        rho = 1.0 + (delta if c == bump else 0.0)
+        want = np.log10(delta / (hmax * rho)) if on_line else -12.0
+        assert abs(f[c, 54] - want) <= 1e-6 * abs(want), (c, f[c, 54], want)
+        assert np.all(f[c, 55:59] == -12.0)
