@@ -11,7 +11,9 @@ Metric: Mcell-stage updates/s = cells x 2 stages x K / timed seconds, for
   * the headline form: FP32-bulk with the learned troubled-cell indicator (GENO where the network
     flags a cell), or FP32-bulk GENO everywhere when no trained indicator is present;
   * FP64 plain (GENO everywhere), measured beside it; the line reports the speedup and the relative
-    L2 difference of the two velocity fields after the same steps.
+    L2 difference of the two velocity fields after the same steps;
+  * with a trained indicator, FP32-bulk GENO everywhere as context (the form without the switch) and
+    the flagged fraction of the learned run.
 The roofline object is for the face-flux kernel (the dominant one): algorithmic flops per launch
 (flops.json, counted from the kernel's own templates) over its mean launch time, taken with HIP events
 on the library's stream during the timed region.  cpu_baseline times the FP64 oracle on host cores
@@ -158,6 +160,12 @@ def main():
     head = run_variant(head_case, cgks.PREC_FP32_BULK, args.steps, args.warmup, True, indicator)
     rate = N * 2 * head["steps"] / head["seconds"] / 1e6
 
+    # context: FP32-bulk with GENO everywhere (the same form without the learned switch)
+    geno32 = None
+    if indicator is not None and not args.no_fp64:
+        geno32 = run_variant(base.with_(recon=cgks.RECON_NONLINEAR), cgks.PREC_FP32_BULK, args.steps,
+                             args.warmup, False)
+
     fp64 = None
     if not args.no_fp64:
         fp64 = run_variant(base.with_(recon=cgks.RECON_NONLINEAR), cgks.PREC_FP64, args.steps, args.warmup, True)
@@ -193,6 +201,15 @@ def main():
         "roofline": roof,
         "kernels_ms": kernels,
     }
+    if indicator is not None:
+        line["learned"] = {"flagged_fraction_last_stage": round(head["diag"]["flagged_fraction"], 4),
+                           "logit_threshold": indicator[1]}
+        if geno32 is not None:
+            r32 = N * 2 * geno32["steps"] / geno32["seconds"] / 1e6
+            dv32 = np.sqrt(((head["vel"] - geno32["vel"]) ** 2).sum()) / np.sqrt((geno32["vel"] ** 2).sum())
+            line["fp32_geno_everywhere"] = {"value": round(r32, 3),
+                                            "ms_per_step": round(geno32["seconds"] / geno32["steps"] * 1e3, 3),
+                                            "rel_l2_velocity_diff_to_learned": float(dv32)}
     if fp64 is not None:
         rate64 = N * 2 * fp64["steps"] / fp64["seconds"] / 1e6
         dv = np.sqrt(((head["vel"] - fp64["vel"]) ** 2).sum()) / np.sqrt((fp64["vel"] ** 2).sum())

@@ -64,6 +64,7 @@ def lib():
         L.cgkso_stencil_offsets.argtypes = [P]
         L.cgkso_recon_cell.argtypes = [ctypes.POINTER(Params), P, P, P, D, I, P, P]
         L.cgkso_face_gauss_points.argtypes = [P]
+        L.cgkso_stage_cells.argtypes = [ctypes.c_void_p, D, P, ctypes.c_long, P, P, P, P]
         L.cgkso_geno_scale.argtypes = [P, I]
         L.cgkso_geno_scale.restype = D
         L.cgkso_indicator_set.argtypes = [P, P, ctypes.c_size_t, D]
@@ -135,6 +136,16 @@ class Oracle:
         L = np.empty((5, self.N)); Lt = np.empty((5, self.N))
         sqn = np.empty((15, self.N)); sqt = np.empty((15, self.N))
         rc = lib().cgkso_stage(self.h, float(dt), _ptr(L), _ptr(Lt), _ptr(sqn), _ptr(sqt))
+        if rc != 0:
+            raise RuntimeError(rc)
+        return L, Lt, sqn, sqt
+
+    def stage_cells(self, dt, cells):
+        """The stage operator at the given cells only: L[5][n], Lt[5][n], sqn[15][n], sqt[15][n]."""
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        n = cells.size
+        L = np.empty((5, n)); Lt = np.empty((5, n)); sqn = np.empty((15, n)); sqt = np.empty((15, n))
+        rc = lib().cgkso_stage_cells(self.h, float(dt), _ptr(cells), n, _ptr(L), _ptr(Lt), _ptr(sqn), _ptr(sqt))
         if rc != 0:
             raise RuntimeError(rc)
         return L, Lt, sqn, sqt

@@ -55,6 +55,11 @@ int  cgkso_compute_dt(void* ctx, double cfl, double* dt);
  * L (5N), dL/dt (5N), Gauss-theorem sums of the interface values Qn (15N) and of their
  * time derivatives Qt (15N).  Any output pointer may be NULL. */
 int  cgkso_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double* sqt);
+/* The CGKS-5th stage operator (as cgkso_stage) at the cells cells[0..n) only, each computed from its
+ * own neighbourhood (reconstructions of the cell and its 6 face neighbours): L[5][n], Lt[5][n],
+ * sqn[15][n], sqt[15][n] (any may be NULL).  LINEAR or NONLINEAR reconstruction; EINVAL otherwise. */
+int  cgkso_stage_cells(void* ctx, double dt, const long* cells, long n, double* L, double* Lt,
+                       double* sqn, double* sqt);
 /* nsteps time steps; the last step is shortened to hit t_stop when t_stop > 0. */
 int  cgkso_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done, double* t_now);
 /* Advance with a prescribed dt (no CFL evaluation). */

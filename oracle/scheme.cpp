@@ -121,6 +121,84 @@ static void compute_flags(Ctx& c, const double* Q, const double* G) {
 // x-faces (x,y,z), y-faces (y,z,x), z-faces (z,x,y).
 static inline int perm(int d, int k) { return (d + k) % 3; }
 
+// Reconstruction of one cell (i, j, k): values and gradients at its 24 face Gauss points,
+// rec[((f * 4 + gp) * 5 + v) * 4 + o], o = value, d/dx, d/dy, d/dz.
+static void recon_one(const Ctx& c, const double* Q, const double* G, long i, long j, long k,
+                      double rec[480]) {
+  const cgkso_params& P = c.P;
+  const long N = c.N;
+  int off[NSTEN][3];
+  stencil_offsets(off);
+  const long ci = cell_index(c, i, j, k);
+  long sc[NSTEN];
+  for (int s = 0; s < NSTEN; ++s) sc[s] = cell_index(c, i + off[s][0], j + off[s][1], k + off[s][2]);
+  int mode = 0;
+  if (P.recon == CGKSO_RECON_NONLINEAR) mode = 1;
+  if (P.recon == CGKSO_RECON_LEARNED) mode = c.flags[ci] ? 1 : 0;
+  double q5[5];
+  for (int v = 0; v < 5; ++v) q5[v] = Q[v * N + ci];
+  for (int v = 0; v < 5; ++v) {
+    double q[NSTEN], g[NSTEN][3];
+    for (int s = 0; s < NSTEN; ++s) {
+      q[s] = Q[v * N + sc[s]];
+      for (int e = 0; e < 3; ++e) g[s][e] = G[(5 * e + v) * N + sc[s]];
+    }
+    double out[6][4][4];
+    recon_cell(P, q, g, c.h, geno_scale(q5, v), mode, out, nullptr);
+    for (int f = 0; f < 6; ++f)
+      for (int gp = 0; gp < 4; ++gp)
+        for (int o = 0; o < 4; ++o) rec[((f * 4 + gp) * 5 + v) * 4 + o] = out[f][gp][o];
+  }
+}
+
+// Flux through the face of axis d between the cells with reconstructions recl (low side, its + face)
+// and recr (high side, its - face), averaged over the 4 Gauss points: acc[30] = F^n, F_t and the
+// interface values Q^n, Q_t of the low and the high side, in the global frame.
+static void face_flux(const cgkso_params& P, double dt, int d, const double* recl, const double* recr,
+                      double acc[30]) {
+  for (int n = 0; n < 30; ++n) acc[n] = 0.0;
+  for (int gp = 0; gp < 4; ++gp) {
+    double wl[20], wr[20];
+    const double* rl = recl + ((2 * d + 1) * 4 + gp) * 20;  // + face of the low cell
+    const double* rr = recr + ((2 * d) * 4 + gp) * 20;      // - face of the high cell
+    for (int side = 0; side < 2; ++side) {
+      const double* r = side ? rr : rl;
+      double* w = side ? wr : wl;
+      for (int v = 0; v < 5; ++v) {
+        // conservative variable v in the face frame: momentum components permuted
+        const int vg = (v >= 1 && v <= 3) ? 1 + perm(d, v - 1) : v;
+        w[v] = r[vg * 4 + 0];
+        for (int dd = 0; dd < 3; ++dd) w[5 + 5 * dd + v] = r[vg * 4 + 1 + perm(d, dd)];
+      }
+    }
+    double o[30];
+    point_flux(P, dt, wl, wr, o, nullptr);
+    for (int blk = 0; blk < 6; ++blk)
+      for (int v = 0; v < 5; ++v) {
+        const int vg = (v >= 1 && v <= 3) ? 1 + perm(d, v - 1) : v;
+        acc[blk * 5 + vg] += 0.25 * o[blk * 5 + v];
+      }
+  }
+}
+
+// Assembly of one cell from its 3 low faces fm[d] and 3 high faces fp[d]: L, dL/dt and the
+// Gauss-theorem sums of the interface values (this cell is the high side of its - face and the low
+// side of its + face).  Outputs at out[v * stride], out[(5 d + v) * stride].
+static void assemble_one(const Ctx& c, const double* fm[3], const double* fp[3], long stride,
+                         double* L, double* Lt, double* sqn, double* sqt) {
+  for (int v = 0; v < 5; ++v) {
+    double l = 0.0, lt = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      l -= (fp[d][v] - fm[d][v]) / c.h[d];
+      lt -= (fp[d][5 + v] - fm[d][5 + v]) / c.h[d];
+      if (sqn) sqn[(5 * d + v) * stride] = (fp[d][10 + v] - fm[d][20 + v]) / c.h[d];
+      if (sqt) sqt[(5 * d + v) * stride] = (fp[d][15 + v] - fm[d][25 + v]) / c.h[d];
+    }
+    if (L) L[v * stride] = l;
+    if (Lt) Lt[v * stride] = lt;
+  }
+}
+
 // One stage of CGKS-5th on (Q, G) with step size dt.  With the learned indicator the flags are
 // evaluated on the stage's input when new_flags is set; the second stage of a step keeps those of
 // the first (the indicator is evaluated once per time step, on Q^n).
@@ -128,8 +206,6 @@ static void stage_cgks5(Ctx& c, const double* Q, const double* G, double dt, dou
                         double* sqn, double* sqt, bool new_flags = true) {
   const cgkso_params& P = c.P;
   const long N = c.N;
-  int off[NSTEN][3];
-  stencil_offsets(off);
   if (new_flags) compute_flags(c, Q, G);
 
   // reconstructed values and gradients at the 24 face Gauss points of every cell
@@ -137,28 +213,7 @@ static void stage_cgks5(Ctx& c, const double* Q, const double* G, double dt, dou
 #pragma omp parallel for collapse(2)
   for (long k = 0; k < P.nz; ++k)
     for (long j = 0; j < P.ny; ++j)
-      for (long i = 0; i < P.nx; ++i) {
-        const long ci = cell_index(c, i, j, k);
-        long sc[NSTEN];
-        for (int s = 0; s < NSTEN; ++s) sc[s] = cell_index(c, i + off[s][0], j + off[s][1], k + off[s][2]);
-        int mode = 0;
-        if (P.recon == CGKSO_RECON_NONLINEAR) mode = 1;
-        if (P.recon == CGKSO_RECON_LEARNED) mode = c.flags[ci] ? 1 : 0;
-        double q5[5];
-        for (int v = 0; v < 5; ++v) q5[v] = Q[v * N + ci];
-        for (int v = 0; v < 5; ++v) {
-          double q[NSTEN], g[NSTEN][3];
-          for (int s = 0; s < NSTEN; ++s) {
-            q[s] = Q[v * N + sc[s]];
-            for (int e = 0; e < 3; ++e) g[s][e] = G[(5 * e + v) * N + sc[s]];
-          }
-          double out[6][4][4];
-          recon_cell(P, q, g, c.h, geno_scale(q5, v), mode, out, nullptr);
-          for (int f = 0; f < 6; ++f)
-            for (int gp = 0; gp < 4; ++gp)
-              for (int o = 0; o < 4; ++o) rec[ci * 480 + ((f * 4 + gp) * 5 + v) * 4 + o] = out[f][gp][o];
-        }
-      }
+      for (long i = 0; i < P.nx; ++i) recon_one(c, Q, G, i, j, k, &rec[cell_index(c, i, j, k) * 480]);
 
   // fluxes on the low face of every cell in each direction, averaged over its Gauss points
   std::vector<double> face(3 * N * 30);
@@ -169,30 +224,7 @@ static void stage_cgks5(Ctx& c, const double* Q, const double* G, double dt, dou
         for (int d = 0; d < 3; ++d) {
           const long cr = cell_index(c, i, j, k);
           const long cl = cell_index(c, i - (d == 0), j - (d == 1), k - (d == 2));
-          double acc[30] = {0.0};
-          for (int gp = 0; gp < 4; ++gp) {
-            double wl[20], wr[20];
-            const double* rl = &rec[cl * 480 + ((2 * d + 1) * 4 + gp) * 20];  // + face of left cell
-            const double* rr = &rec[cr * 480 + ((2 * d) * 4 + gp) * 20];      // - face of right cell
-            for (int side = 0; side < 2; ++side) {
-              const double* r = side ? rr : rl;
-              double* w = side ? wr : wl;
-              for (int v = 0; v < 5; ++v) {
-                // conservative variable v in the face frame: momentum components permuted
-                const int vg = (v >= 1 && v <= 3) ? 1 + perm(d, v - 1) : v;
-                w[v] = r[vg * 4 + 0];
-                for (int dd = 0; dd < 3; ++dd) w[5 + 5 * dd + v] = r[vg * 4 + 1 + perm(d, dd)];
-              }
-            }
-            double o[30];
-            point_flux(P, dt, wl, wr, o, nullptr);
-            for (int blk = 0; blk < 6; ++blk)
-              for (int v = 0; v < 5; ++v) {
-                const int vg = (v >= 1 && v <= 3) ? 1 + perm(d, v - 1) : v;
-                acc[blk * 5 + vg] += 0.25 * o[blk * 5 + v];
-              }
-          }
-          for (int n = 0; n < 30; ++n) face[(d * N + cr) * 30 + n] = acc[n];
+          face_flux(P, dt, d, &rec[cl * 480], &rec[cr * 480], &face[(d * N + cr) * 30]);
         }
 
   // assembly
@@ -201,22 +233,43 @@ static void stage_cgks5(Ctx& c, const double* Q, const double* G, double dt, dou
     for (long j = 0; j < P.ny; ++j)
       for (long i = 0; i < P.nx; ++i) {
         const long ci = cell_index(c, i, j, k);
-        for (int v = 0; v < 5; ++v) {
-          double l = 0.0, lt = 0.0;
-          for (int d = 0; d < 3; ++d) {
-            const long cp = cell_index(c, i + (d == 0), j + (d == 1), k + (d == 2));
-            const double* fm = &face[(d * N + ci) * 30];
-            const double* fp = &face[(d * N + cp) * 30];
-            l -= (fp[v] - fm[v]) / c.h[d];
-            lt -= (fp[5 + v] - fm[5 + v]) / c.h[d];
-            // this cell is the left cell of its + face and the right cell of its - face
-            if (sqn) sqn[(5 * d + v) * N + ci] = (fp[10 + v] - fm[20 + v]) / c.h[d];
-            if (sqt) sqt[(5 * d + v) * N + ci] = (fp[15 + v] - fm[25 + v]) / c.h[d];
-          }
-          if (L) L[v * N + ci] = l;
-          if (Lt) Lt[v * N + ci] = lt;
+        const double *fm[3], *fp[3];
+        for (int d = 0; d < 3; ++d) {
+          fm[d] = &face[(d * N + ci) * 30];
+          fp[d] = &face[(d * N + cell_index(c, i + (d == 0), j + (d == 1), k + (d == 2))) * 30];
         }
+        assemble_one(c, fm, fp, N, L ? L + ci : nullptr, Lt ? Lt + ci : nullptr,
+                     sqn ? sqn + ci : nullptr, sqt ? sqt + ci : nullptr);
       }
+}
+
+// The same stage at a list of cells only, each from its own neighbourhood: the reconstructions of
+// the cell and its 6 face neighbours, the 6 face fluxes, the assembly.  Outputs [5][n], [15][n].
+static void stage_cgks5_cells(const Ctx& c, const double* Q, const double* G, double dt,
+                              const long* cells, long n, double* L, double* Lt, double* sqn,
+                              double* sqt) {
+  const cgkso_params& P = c.P;
+#pragma omp parallel for
+  for (long m = 0; m < n; ++m) {
+    const long ci = cells[m];
+    const long i = ci % P.nx, j = (ci / P.nx) % P.ny, k = ci / ((long)P.nx * P.ny);
+    std::vector<double> rc(480), rn(6 * 480);
+    recon_one(c, Q, G, i, j, k, rc.data());
+    for (int f = 0; f < 6; ++f) {
+      const int d = f / 2, sgn = (f % 2) ? 1 : -1;
+      recon_one(c, Q, G, i + (d == 0) * sgn, j + (d == 1) * sgn, k + (d == 2) * sgn, &rn[f * 480]);
+    }
+    double fmv[3][30], fpv[3][30];
+    const double *fm[3], *fp[3];
+    for (int d = 0; d < 3; ++d) {
+      face_flux(P, dt, d, &rn[(2 * d) * 480], rc.data(), fmv[d]);      // low face: neighbour | cell
+      face_flux(P, dt, d, rc.data(), &rn[(2 * d + 1) * 480], fpv[d]);  // high face: cell | neighbour
+      fm[d] = fmv[d];
+      fp[d] = fpv[d];
+    }
+    assemble_one(c, fm, fp, n, L ? L + m : nullptr, Lt ? Lt + m : nullptr, sqn ? sqn + m : nullptr,
+                 sqt ? sqt + m : nullptr);
+  }
 }
 
 // One stage of GKS-2nd on Q (face-midpoint fluxes).
@@ -405,6 +458,18 @@ int cgkso_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double
     stage_gks2(*c, c->Q.data(), dt, L, Lt);
   else
     stage_cgks5(*c, c->Q.data(), c->G.data(), dt, L, Lt, sqn, sqt);
+  return CGKSO_OK;
+}
+
+int cgkso_stage_cells(void* ctx, double dt, const long* cells, long n, double* L, double* Lt,
+                      double* sqn, double* sqt) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c->have_state) return CGKSO_ESTATE;
+  if (c->P.scheme != CGKSO_SCHEME_CGKS5 || c->P.recon == CGKSO_RECON_LEARNED || !cells || n < 0)
+    return CGKSO_EINVAL;
+  for (long m = 0; m < n; ++m)
+    if (cells[m] < 0 || cells[m] >= c->N) return CGKSO_EINVAL;
+  stage_cgks5_cells(*c, c->Q.data(), c->G.data(), dt, cells, n, L, Lt, sqn, sqt);
   return CGKSO_OK;
 }
 

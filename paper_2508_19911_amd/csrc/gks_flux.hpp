@@ -75,29 +75,30 @@ __host__ __device__ __forceinline__ void maxwell_moments(const Prim<T>& p, T Kdo
   m.xi4 = Kdof * (Kdof + T(2)) * var * var;
 }
 
-// <u^A v^B w^C psi>, psi = (1, u, v, w, (u^2+v^2+w^2+xi^2)/2)
+// <u^A v^B w^C psi>, psi = (1, u, v, w, (u^2+v^2+w^2+xi^2)/2).  Products are formed as
+// <u^A> (<v^B> <w^C>): the tangential pairs are few and shared by every normal order A.
 template <int A, int B, int C, class T>
 __host__ __device__ __forceinline__ void mvec(const Mom<T>& m, T o[5]) {
-  const T b = m.u[A] * m.v[B] * m.w[C];
+  const T vw = m.v[B] * m.w[C];
+  const T b = m.u[A] * vw;
   o[0] = b;
-  o[1] = m.u[A + 1] * m.v[B] * m.w[C];
-  o[2] = m.u[A] * m.v[B + 1] * m.w[C];
-  o[3] = m.u[A] * m.v[B] * m.w[C + 1];
-  o[4] = T(0.5) * (m.u[A + 2] * m.v[B] * m.w[C] + m.u[A] * m.v[B + 2] * m.w[C] +
-                   m.u[A] * m.v[B] * m.w[C + 2] + b * m.xi2);
+  o[1] = m.u[A + 1] * vw;
+  o[2] = m.u[A] * (m.v[B + 1] * m.w[C]);
+  o[3] = m.u[A] * (m.v[B] * m.w[C + 1]);
+  o[4] = T(0.5) * (m.u[A + 2] * vw + m.u[A] * (m.v[B + 2] * m.w[C]) + m.u[A] * (m.v[B] * m.w[C + 2]) +
+                   b * m.xi2);
 }
 
 // <xi^2 u^A v^B w^C psi>
 template <int A, int B, int C, class T>
 __host__ __device__ __forceinline__ void mvec_xi(const Mom<T>& m, T o[5]) {
-  const T b = m.u[A] * m.v[B] * m.w[C];
-  o[0] = m.xi2 * b;
-  o[1] = m.xi2 * m.u[A + 1] * m.v[B] * m.w[C];
-  o[2] = m.xi2 * m.u[A] * m.v[B + 1] * m.w[C];
-  o[3] = m.xi2 * m.u[A] * m.v[B] * m.w[C + 1];
-  o[4] = T(0.5) * (m.xi2 * (m.u[A + 2] * m.v[B] * m.w[C] + m.u[A] * m.v[B + 2] * m.w[C] +
-                            m.u[A] * m.v[B] * m.w[C + 2]) +
-                   m.xi4 * b);
+  T t[5];
+  mvec<A, B, C>(m, t);
+  const T b = t[0];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) o[i] = m.xi2 * t[i];
+  // <xi^2 psi_4> = (xi2 <(u^2+v^2+w^2) ...> + xi4 <...>)/2 = xi2 (t4 - b xi2/2) + xi4 b/2
+  o[4] = m.xi2 * (t[4] - T(0.5) * b * m.xi2) + T(0.5) * m.xi4 * b;
 }
 
 // <s u^A v^B w^C psi> for the slope polynomial s = s1 + s2 u + s3 v + s4 w + s5 (u^2+v^2+w^2+xi^2)/2;

@@ -219,3 +219,18 @@ def test_tgv_initial_diagnostics_closed_forms():
         assert d["epsD"] <= 1e-12 * d["epsS"]
     e16, e32 = np.array(errs[0]), np.array(errs[1])
     assert np.all(np.abs(e32) < 1.5e-2) and np.all(np.abs(e16 / e32) > 3.5), errs
+
+
+@pytest.mark.parametrize("recon", [0, 1])
+def test_stage_at_cells_equals_whole_grid_stage(recon):
+    """The per-cell stage (each cell from its own neighbourhood) is the same arithmetic as the
+    whole-grid stage: equal bitwise at every cell, including the periodic wrap at the box edges."""
+    case = inputs.tgv_case(6, ma=0.3).with_(recon=recon, nx=7, ny=6, nz=5, lx=2.1, ly=1.7, lz=1.4)
+    q, g = inputs.seeded_smooth_state(case, seed=5, amp=0.2)
+    o = make(case); o.set_state(q, g)
+    dt = o.compute_dt(0.5)
+    full = o.stage(dt)
+    cells = np.array([0, case.N - 1, 6, 41, 7 * 6 * 4, 100, 123])
+    part = o.stage_cells(dt, cells)
+    for a, b in zip(full, part):
+        assert np.array_equal(a[:, cells], b)
