@@ -65,6 +65,46 @@ __host__ __device__ __forceinline__ void st(T* __restrict__ base, uint32_t idx, 
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T)) = v;
 }
 
+// Plane accessors for gathers.  PtrPlane reads through a pointer (host instantiations, such as the
+// flop counter).  BufPlane (device) reads through a buffer resource: the plane's base and size sit
+// in scalar registers and each lane supplies a 32-bit byte offset, so a gather of many planes at the
+// same offsets needs no per-load address arithmetic; a read beyond the plane returns 0.
+template <class T>
+struct PtrPlane {
+  const T* p;
+  __host__ __device__ T operator()(uint32_t byte_off) const {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
+  }
+};
+constexpr int BUFFER_RSRC_WORD3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
+template <class T>
+struct BufPlane {
+#ifdef __HIP_DEVICE_COMPILE__
+  __amdgpu_buffer_rsrc_t r;
+#else
+  const T* p;  // the host pass only parses device code
+#endif
+  __device__ BufPlane(const T* base, long long n) {
+#ifdef __HIP_DEVICE_COMPILE__
+    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)(n * (long long)sizeof(T)),
+                                          BUFFER_RSRC_WORD3);
+#else
+    p = base;
+    (void)n;
+#endif
+  }
+  __device__ T operator()(uint32_t byte_off) const {
+#ifdef __HIP_DEVICE_COMPILE__
+    if constexpr (sizeof(T) == 8)
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+    else
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+#else
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
+#endif
+  }
+};
+
 // face-frame permutation: the face of axis d sees (normal, t1, t2) = axes (d, d+1, d+2) mod 3
 __host__ __device__ constexpr int perm(int d, int k) { return (d + k) % 3; }
 

@@ -160,9 +160,12 @@ int main() {
   const int N = 27;
   static double Qv[27];
   static Fl Gv[3 * 27];
-  int sidx[19];
-  for (int s = 0; s < 19; ++s)
-    sidx[s] = (tab::SOFF[s][2] + 1) * 9 + (tab::SOFF[s][1] + 1) * 3 + (tab::SOFF[s][0] + 1);
+  uint32_t oq[19], og[19];
+  for (int s = 0; s < 19; ++s) {
+    const uint32_t c = (tab::SOFF[s][2] + 1) * 9 + (tab::SOFF[s][1] + 1) * 3 + (tab::SOFF[s][0] + 1);
+    oq[s] = c * (uint32_t)sizeof(double);
+    og[s] = c * (uint32_t)sizeof(Fl);
+  }
   Grid g{3, 3, 3, 27, {0.1, 0.1, 0.1}, {10, 10, 10}};
   Fl dface[6], g0[3];
   reset();
@@ -171,7 +174,9 @@ int main() {
     for (int e = 0; e < 3; ++e) Gv[e * N + c] = leaf(0.02 * c + e);
   }
   for (int m = 0; m < 34; ++m) a[m] = Fl(0.0);
-  gather_coefficients<Fl>(g, Qv, Gv, N, sidx, Qv[13], a, dface, g0);
+  const PtrPlane<double> qa{Qv};
+  const PtrPlane<Fl> ga[3] = {{Gv}, {Gv + N}, {Gv + 2 * N}};
+  gather_coefficients<Fl>(g, qa, ga, oq, og, Qv[13], a, dface, g0);
   const long long coef_var = fc::n_flop + 18;
   const long long geno_base = fc::n_flop;
   geno_blend(dface, g0, a, GenoParams{0.85, 1e-15, 0.01}, leaf(0.01));

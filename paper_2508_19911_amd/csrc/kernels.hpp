@@ -72,23 +72,22 @@ struct CoefBlock {
 
 // ============================================================================ reconstruction
 // Gather the stencil of one variable and accumulate a = R d column by column; the face-neighbour
-// differences and the cell's own normalised gradient are kept for GENO.
-template <class T, int S = 0>
-__host__ __device__ __forceinline__ void gather_coefficients(const Grid& g, const double* __restrict__ Qv,
-                                                    const T* __restrict__ Gv, long long N,
-                                                    const int* sidx, double q0, T* a, T* dface,
-                                                    T* g0) {
+// differences and the cell's own normalised gradient are kept for GENO.  qa reads the variable's
+// average plane and ga[3] its three gradient planes; oq[s], og[s] are the byte offsets of stencil
+// cell s in a plane of double and of T.
+template <class T, int S = 0, class QA, class GA>
+__host__ __device__ __forceinline__ void gather_coefficients(const Grid& g, const QA& qa, const GA* ga,
+                                                             const uint32_t* oq, const uint32_t* og,
+                                                             double q0, T* a, T* dface, T* g0) {
   if constexpr (S < tab::NSTEN) {
-    const uint32_t c = (uint32_t)sidx[S];
     if constexpr (S != tab::CENTRE) {
-      const T x = data<T>(ld(Qv, c) - q0);
+      const T x = data<T>(qa(oq[S]) - q0);
       op_col<tab::NEIGH_SLOT[S]>(x, a);
 #pragma unroll
       for (int f = 0; f < 6; ++f)
         if (face_slot(f) == tab::NEIGH_SLOT[S]) dface[f] = x;
     }
-    const T gx = T(g.h[0]) * ld(Gv, c), gy = T(g.h[1]) * ld(Gv + N, c),
-            gz = T(g.h[2]) * ld(Gv + 2 * N, c);
+    const T gx = T(g.h[0]) * ga[0](og[S]), gy = T(g.h[1]) * ga[1](og[S]), gz = T(g.h[2]) * ga[2](og[S]);
     op_col<18 + 3 * S + 0>(gx, a);
     op_col<18 + 3 * S + 1>(gy, a);
     op_col<18 + 3 * S + 2>(gz, a);
@@ -101,7 +100,7 @@ __host__ __device__ __forceinline__ void gather_coefficients(const Grid& g, cons
     // one stencil cell at a time: the scheduler may not hoist its loads above the previous cell
     __builtin_amdgcn_sched_barrier(0);
 #endif
-    gather_coefficients<T, S + 1>(g, Qv, Gv, N, sidx, q0, a, dface, g0);
+    gather_coefficients<T, S + 1>(g, qa, ga, oq, og, q0, a, dface, g0);
   }
 }
 
@@ -115,11 +114,15 @@ __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__
   int i, j, k;
   cell_ijk(g, cell, i, j, k);
   const long long N = g.N;
-  int sidx[tab::NSTEN];
+  // byte offsets of the 19 stencil cells in a plane of double and in a plane of T
+  uint32_t oq[tab::NSTEN], og[tab::NSTEN];
 #pragma unroll
-  for (int s = 0; s < tab::NSTEN; ++s)
-    sidx[s] = (wrap_o(k, tab::SOFF[s][2], g.nz) * g.ny + wrap_o(j, tab::SOFF[s][1], g.ny)) * g.nx +
-              wrap_o(i, tab::SOFF[s][0], g.nx);
+  for (int s = 0; s < tab::NSTEN; ++s) {
+    const uint32_t c = (uint32_t)((wrap_o(k, tab::SOFF[s][2], g.nz) * g.ny + wrap_o(j, tab::SOFF[s][1], g.ny)) *
+                                      g.nx + wrap_o(i, tab::SOFF[s][0], g.nx));
+    oq[s] = c * 8u;
+    og[s] = c * (uint32_t)sizeof(T);
+  }
   bool geno = MODE == 1;
   if constexpr (MODE == 2) geno = flags[cell] != 0;
   double q5[5];
@@ -127,11 +130,13 @@ __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__
   for (int v = 0; v < 5; ++v) q5[v] = ld(Q + v * N, (uint32_t)cell);
 #pragma unroll 1
   for (int v = 0; v < 5; ++v) {
-    const double* Qv = Q + v * N;
+    const BufPlane<double> qa(Q + v * N, N);
+    const BufPlane<T> ga[3] = {BufPlane<T>(G + v * N, N), BufPlane<T>(G + (5 + v) * N, N),
+                               BufPlane<T>(G + (10 + v) * N, N)};
     T a[tab::NB], dface[6], g0[3];
 #pragma unroll
     for (int m = 0; m < tab::NB; ++m) a[m] = T(0);
-    gather_coefficients<T>(g, Qv, G + v * N, 5 * N, sidx, ld(Qv, (uint32_t)cell), a, dface, g0);
+    gather_coefficients<T>(g, qa, ga, oq, og, q5[v], a, dface, g0);
     if (MODE != 0 && geno) geno_blend(dface, g0, a, gp, data<T>(gp.eps + gp.hmax2 * geno_scale(q5, v)));
     using CB = CoefBlock<T>;
     using V = typename Vec16<T>::type;

@@ -63,26 +63,40 @@ __device__ __forceinline__ void cell_features(const Grid& g, const double* __res
   j = jk % g.ny;
   k = jk / g.ny;
   const long long N = g.N;
+  // byte offsets of the line cells o = -2..2 along each axis, in planes of double and of T
+  uint32_t oq[3][5], og[3][5];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int o = -2; o <= 2; ++o) {
+      const int ii = d == 0 ? wrap_o(i, o, g.nx) : i;
+      const int jj = d == 1 ? wrap_o(j, o, g.ny) : j;
+      const int kk = d == 2 ? wrap_o(k, o, g.nz) : k;
+      const uint32_t c = (uint32_t)((kk * g.ny + jj) * g.nx + ii);
+      oq[d][o + 2] = c * 8u;
+      og[d][o + 2] = c * (uint32_t)sizeof(T);
+    }
+  double q5[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) q5[v] = Q[v * N + cell];
 #pragma unroll
   for (int vi = 0; vi < 2; ++vi) {
     const int v = vi ? 4 : 0;
-    const double q0 = Q[v * N + cell];
+    const BufPlane<double> qv(Q + v * N, N);
+    const double q0 = q5[v];
     double dv[3][4], gv[3][5];
     double mxd = 0.0, mxg = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
+      const BufPlane<T> gd(G + (d * 5 + v) * N, N);
 #pragma unroll
       for (int o = -2; o <= 2; ++o) {
-        const int ii = d == 0 ? wrap_o(i, o, g.nx) : i;
-        const int jj = d == 1 ? wrap_o(j, o, g.ny) : j;
-        const int kk = d == 2 ? wrap_o(k, o, g.nz) : k;
-        const int c = (kk * g.ny + jj) * g.nx + ii;
         if (o != 0) {
-          const double dd = Q[v * N + c] - q0;
+          const double dd = qv(oq[d][o + 2]) - q0;
           dv[d][o < 0 ? o + 2 : o + 1] = dd;
           mxd = fmax(mxd, fabs(dd));
         }
-        const double gg = g.h[d] * double(G[(d * 5 + v) * N + c]);
+        const double gg = g.h[d] * double(gd(og[d][o + 2]));
         gv[d][o + 2] = gg;
         mxg = fmax(mxg, fabs(gg));
       }
@@ -98,28 +112,22 @@ __device__ __forceinline__ void cell_features(const Grid& g, const double* __res
   }
   // features 54..58: per conservative variable, log10 of the largest difference or h dQ on the same
   // lines over h_max sqrt(S_v), S_v the variable's GENO scale (clipped below at -12)
-  {
-    double q5[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) q5[v] = Q[v * N + cell];
-    const double hmax = fmax(g.h[0], fmax(g.h[1], g.h[2]));
+  const double hmax = fmax(g.h[0], fmax(g.h[1], g.h[2]));
 #pragma unroll 1
-    for (int v = 0; v < 5; ++v) {
-      double mx = 0.0;
+  for (int v = 0; v < 5; ++v) {
+    const BufPlane<double> qv(Q + v * N, N);
+    double mx = 0.0;
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < 3; ++d) {
+      const BufPlane<T> gd(G + (d * 5 + v) * N, N);
 #pragma unroll
-        for (int o = -2; o <= 2; ++o) {
-          const int ii = d == 0 ? wrap_o(i, o, g.nx) : i;
-          const int jj = d == 1 ? wrap_o(j, o, g.ny) : j;
-          const int kk = d == 2 ? wrap_o(k, o, g.nz) : k;
-          const int c = (kk * g.ny + jj) * g.nx + ii;
-          mx = fmax(mx, fabs(Q[v * N + c] - q5[v]));
-          mx = fmax(mx, fabs(g.h[d] * double(G[(d * 5 + v) * N + c])));
-        }
-      // the ratio in FP64, its logarithm in FP32 (a feature needs no more)
-      f[54 + v] = fmaxf(log10f(float(mx / (hmax * sqrt(geno_scale(q5, v))))), -12.0f);
+      for (int o = 0; o < 5; ++o) {
+        mx = fmax(mx, fabs(qv(oq[d][o]) - q5[v]));
+        mx = fmax(mx, fabs(g.h[d] * double(gd(og[d][o]))));
+      }
     }
+    // the ratio in FP64, its logarithm in FP32 (a feature needs no more)
+    f[54 + v] = fmaxf(log10f(float(mx / (hmax * sqrt(geno_scale(q5, v))))), -12.0f);
   }
 #pragma unroll
   for (int n = 59; n < 64; ++n) f[n] = 0.0f;
@@ -153,22 +161,27 @@ __global__ __launch_bounds__(256) void k_labels(Grid g, const double* __restrict
   const int jk = cell / g.nx;
   int j = jk % g.ny, k = jk / g.ny;
   const long long N = g.N;
-  int sidx[tab::NSTEN];
+  uint32_t oq[tab::NSTEN], og[tab::NSTEN];
 #pragma unroll
-  for (int s = 0; s < tab::NSTEN; ++s)
-    sidx[s] = (wrap_o(k, tab::SOFF[s][2], g.nz) * g.ny + wrap_o(j, tab::SOFF[s][1], g.ny)) * g.nx +
-              wrap_o(i, tab::SOFF[s][0], g.nx);
+  for (int s = 0; s < tab::NSTEN; ++s) {
+    const uint32_t c = (uint32_t)((wrap_o(k, tab::SOFF[s][2], g.nz) * g.ny + wrap_o(j, tab::SOFF[s][1], g.ny)) *
+                                      g.nx + wrap_o(i, tab::SOFF[s][0], g.nx));
+    oq[s] = c * 8u;
+    og[s] = c * (uint32_t)sizeof(T);
+  }
   double worst = 0.0;
   double q5[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) q5[v] = Q[v * N + cell];
 #pragma unroll 1
   for (int v = 0; v < 5; ++v) {
-    const double* Qv = Q + v * N;
+    const BufPlane<double> qa(Q + v * N, N);
+    const BufPlane<T> ga[3] = {BufPlane<T>(G + v * N, N), BufPlane<T>(G + (5 + v) * N, N),
+                               BufPlane<T>(G + (10 + v) * N, N)};
     T a[tab::NB], dface[6], g0[3];
 #pragma unroll
     for (int m = 0; m < tab::NB; ++m) a[m] = T(0);
-    gather_coefficients<T>(g, Qv, G + v * N, 5 * N, sidx, Qv[cell], a, dface, g0);
+    gather_coefficients<T>(g, qa, ga, oq, og, q5[v], a, dface, g0);
     const T chi = geno_blend(dface, g0, a, gp, data<T>(gp.eps + gp.hmax2 * geno_scale(q5, v)));
     worst = fmax(worst, fabs(1.0 - double(chi)));
   }
