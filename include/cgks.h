@@ -52,7 +52,8 @@ enum { CGKS_PREC_FP64 = 0, CGKS_PREC_FP32_BULK = 1 };
 enum { CGKS_IC_VORTEX2D = 0, CGKS_IC_TGV = 1, CGKS_IC_TGV_SUPERSONIC = 2 };
 
 typedef struct {
-  int nx, ny, nz;           /* cells per direction (>= 1; nz == 1 runs the 3-D scheme on a 2-D field) */
+  int nx, ny, nz;           /* cells per direction (>= 1; nz == 1 runs the 3-D scheme on a 2-D field);
+                             nx ny nz < 2^29 (a plane of doubles below 4 GiB) */
   double lx, ly, lz;        /* box lengths; h_d = l_d / n_d */
   double gamma;             /* ratio of specific heats (> 1); internal DOF K = (5 - 3 gamma)/(gamma - 1) */
   double mu0;               /* reference viscosity; 0 selects the inviscid collision time (Sec. 4) */
@@ -111,6 +112,13 @@ int cgks_step_fixed(void* ctx, int nsteps, double dt);
  * NULL): L[5N], dL/dt[5N] and, for CGKS5, the Gauss-theorem sums sqn[15N], sqt[15N] of the
  * interface values and of their time derivatives.  The state is unchanged. */
 int cgks_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double* sqt);
+/* The same stage operator evaluated on the whole grid on the device, returned only at the cells
+ * cells[0..n) (host array of cell indices, 0 <= cell < N): L[5][n], Lt[5][n] and, for CGKS5,
+ * sqn[15][n], sqt[15][n] (any output may be NULL).  For grids whose full outputs would not fit host
+ * memory (512^3: 43 GB).  The face planes of the workspace stage the indices and results, which
+ * bounds n by about N/3 (EINVAL beyond, or for a cell out of range).  The state is unchanged. */
+int cgks_stage_sampled(void* ctx, double dt, const long* cells, long n, double* L, double* Lt,
+                       double* sqn, double* sqt);
 
 int cgks_diagnostics(void* ctx, double rho0, double u0, cgks_diag* out);
 /* Flags (1 byte per cell): the cells on which the nonlinear blend ran in the last stage (GENO, or

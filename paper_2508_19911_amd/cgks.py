@@ -24,7 +24,7 @@ ERRORS = {0: "ok", -1: "EINVAL", -2: "EWORKSPACE", -3: "EDEVICE", -4: "ENONPHYSI
 # every entry point declared in include/cgks.h
 SYMBOLS = [
     "cgks_workspace_bytes", "cgks_create", "cgks_destroy", "cgks_set_state", "cgks_set_ic",
-    "cgks_get_state", "cgks_compute_dt", "cgks_step", "cgks_step_fixed", "cgks_stage",
+    "cgks_get_state", "cgks_compute_dt", "cgks_step", "cgks_step_fixed", "cgks_stage", "cgks_stage_sampled",
     "cgks_diagnostics", "cgks_get_flags", "cgks_indicator_set", "cgks_indicator_get",
     "cgks_features", "cgks_indicator_logits", "cgks_labels", "cgks_indicator_train",
     "cgks_indicator_grad", "cgks_timing_enable", "cgks_timing_read", "cgks_debug_point_flux",
@@ -81,6 +81,7 @@ def load():
     L.cgks_step.argtypes = [P, I, D, D, ctypes.POINTER(I), ctypes.POINTER(D)]
     L.cgks_step_fixed.argtypes = [P, I, D]
     L.cgks_stage.argtypes = [P, D, P, P, P, P]
+    L.cgks_stage_sampled.argtypes = [P, D, P, ctypes.c_long, P, P, P, P]
     L.cgks_diagnostics.argtypes = [P, D, D, ctypes.POINTER(Diag)]
     L.cgks_get_flags.argtypes = [P, P]
     L.cgks_indicator_set.argtypes = [P, P, Z, D]
@@ -184,6 +185,19 @@ class Solver:
         L = np.empty((5, self.N)); Lt = np.empty((5, self.N))
         sqn = np.empty((15, self.N)); sqt = np.empty((15, self.N))
         _check("cgks_stage", load().cgks_stage(self.h, float(dt), _p(L), _p(Lt), _p(sqn), _p(sqt)))
+        return L, Lt, sqn, sqt
+
+    def stage_sampled(self, dt, cells):
+        """The stage operator computed on the device for the whole grid, returned at the given cells:
+        L[5][n], Lt[5][n], sqn[15][n], sqt[15][n] (the last two None for GKS-2nd)."""
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        n = cells.size
+        L = np.empty((5, n)); Lt = np.empty((5, n))
+        c5 = self.case.scheme == SCHEME_CGKS5
+        sqn = np.empty((15, n)) if c5 else None
+        sqt = np.empty((15, n)) if c5 else None
+        _check("cgks_stage_sampled", load().cgks_stage_sampled(
+            self.h, float(dt), _p(cells), n, _p(L), _p(Lt), _p(sqn) if c5 else None, _p(sqt) if c5 else None))
         return L, Lt, sqn, sqt
 
     def diagnostics(self, rho0=1.0, u0=1.0):

@@ -27,7 +27,8 @@ struct Layout {
 bool valid(const cgks_params* p) {
   if (!p) return false;
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
-  if ((long long)p->nx * p->ny * p->nz > (1LL << 29)) return false;  // 32-bit byte offsets per plane
+  // byte offsets and buffer sizes within one plane are 32-bit: a plane of doubles must stay below 4 GiB
+  if ((long long)p->nx * p->ny * p->nz >= (1LL << 29)) return false;
   if (!(p->lx > 0) || !(p->ly > 0) || !(p->lz > 0) || !(p->gamma > 1.0)) return false;
   if (p->scheme != CGKS_SCHEME_CGKS5 && p->scheme != CGKS_SCHEME_GKS2) return false;
   if (p->recon < CGKS_RECON_LINEAR || p->recon > CGKS_RECON_LEARNED) return false;
@@ -550,6 +551,59 @@ int cgks_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double*
   HIPCK(hipStreamSynchronize(c.stream));
   for (size_t n = 0; n < tn.size(); ++n) sqn[n] = tn[n];
   for (size_t n = 0; n < tt.size(); ++n) sqt[n] = tt[n];
+  return CGKS_OK;
+}
+
+int cgks_stage_sampled(void* ctx, double dt, const long* cells, long n, double* L, double* Lt,
+                       double* sqn, double* sqt) {
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_state) return CGKS_ESTATE;
+  if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) return CGKS_ESTATE;
+  if (!(dt > 0.0) || !cells || n <= 0) return CGKS_EINVAL;
+  const bool c5 = c.p.scheme == CGKS_SCHEME_CGKS5;
+  if (!c5 && (sqn || sqt)) return CGKS_EINVAL;
+  for (long m = 0; m < n; ++m)
+    if (cells[m] < 0 || cells[m] >= c.g.N) return CGKS_EINVAL;
+  // staging in the face planes, free once the stage has been assembled: indices, then 40 doubles
+  // per sampled cell
+  const size_t ts = c.p.precision == CGKS_PREC_FP64 ? 8 : 4;
+  const size_t fbytes = (c5 ? 90 : 30) * (size_t)c.g.N * ts;
+  const size_t ibytes = ((size_t)n * 4 + 255) & ~(size_t)255;
+  if (ibytes + 40 * (size_t)n * 8 > fbytes) return CGKS_EINVAL;
+  const bool f64 = c.p.precision == CGKS_PREC_FP64;
+  int rc;
+  if (!c5)
+    rc = f64 ? stage2<double, 1>(c, dt) : stage2<float, 1>(c, dt);
+  else if (f64)
+    rc = stage5<double, 0>(c, c.at<double>(c.L.Q), c.at<double>(c.L.G), dt);
+  else
+    rc = stage5<float, 0>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G), dt);
+  if (rc) return rc;
+  std::vector<uint32_t> idx(cells, cells + n);
+  uint32_t* didx = c.at<uint32_t>(c.L.F);
+  double* dout = reinterpret_cast<double*>(c.ws + c.L.F + ibytes);
+  HIPCK(hipMemcpyAsync(didx, idx.data(), (size_t)n * 4, hipMemcpyHostToDevice, c.stream));
+  const long long N = c.g.N;
+  const dim3 grid((unsigned)((n + BLK - 1) / BLK)), blk(BLK);
+  k_gather_cells<double><<<grid, blk, 0, c.stream>>>(n, didx, c.at<double>(c.L.Acc), 5, N, dout);
+  k_gather_cells<double><<<grid, blk, 0, c.stream>>>(n, didx, c.at<double>(c.L.Qs), 5, N, dout + 5 * n);
+  if (c5) {
+    if (f64) {
+      k_gather_cells<double><<<grid, blk, 0, c.stream>>>(n, didx, c.at<double>(c.L.GQn), 15, N, dout + 10 * n);
+      k_gather_cells<double><<<grid, blk, 0, c.stream>>>(n, didx, c.at<double>(c.L.Gs), 15, N, dout + 25 * n);
+    } else {
+      k_gather_cells<float><<<grid, blk, 0, c.stream>>>(n, didx, c.at<float>(c.L.GQn), 15, N, dout + 10 * n);
+      k_gather_cells<float><<<grid, blk, 0, c.stream>>>(n, didx, c.at<float>(c.L.Gs), 15, N, dout + 25 * n);
+    }
+  }
+  LAUNCHCK("k_gather_cells");
+  std::vector<double> host((size_t)40 * n);
+  HIPCK(hipMemcpyAsync(host.data(), dout, (c5 ? 40 : 10) * (size_t)n * 8, hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  if (L) std::copy(host.begin(), host.begin() + 5 * n, L);
+  if (Lt) std::copy(host.begin() + 5 * n, host.begin() + 10 * n, Lt);
+  if (sqn) std::copy(host.begin() + 10 * n, host.begin() + 25 * n, sqn);
+  if (sqt) std::copy(host.begin() + 25 * n, host.begin() + 40 * n, sqt);
   return CGKS_OK;
 }
 

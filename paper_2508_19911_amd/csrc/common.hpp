@@ -86,8 +86,9 @@ struct BufPlane {
 #endif
   __device__ BufPlane(const T* base, long long n) {
 #ifdef __HIP_DEVICE_COMPILE__
-    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)(n * (long long)sizeof(T)),
-                                          BUFFER_RSRC_WORD3);
+    // size in bytes as a 32-bit field (planes hold fewer than 2^29 elements: below 4 GiB)
+    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0,
+                                          (int)(uint32_t)(n * (long long)sizeof(T)), BUFFER_RSRC_WORD3);
 #else
     p = base;
     (void)n;
@@ -104,6 +105,28 @@ struct BufPlane {
 #endif
   }
 };
+
+// Exchange inside a quad of lanes (DPP quad_perm, a VALU operand modifier; no LDS traffic):
+// QUAD_XOR1 = lanes (1,0,3,2), QUAD_XOR2 = lanes (2,3,0,1).
+constexpr int QUAD_XOR1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);
+constexpr int QUAD_XOR2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
+template <int CTRL>
+__device__ __forceinline__ float quad_perm(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double x) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// sum over the 4 lanes of a quad, in the order (x + x^1) + (x + x^1)^2
+template <class T>
+__device__ __forceinline__ T quad_sum(T x) {
+  x += quad_perm<QUAD_XOR1>(x);
+  return x + quad_perm<QUAD_XOR2>(x);
+}
 
 // face-frame permutation: the face of axis d sees (normal, t1, t2) = axes (d, d+1, d+2) mod 3
 __host__ __device__ constexpr int perm(int d, int k) { return (d + k) % 3; }

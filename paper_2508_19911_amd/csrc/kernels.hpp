@@ -229,12 +229,7 @@ __global__ __launch_bounds__(FLUX_BLK) void k_flux5(Grid g, const double* __rest
   gks_flux<T, 30>(fp, dt, WL, DL, WR, DR, out);
   // 2x2 Gauss average over the four lanes of the face
 #pragma unroll
-  for (int n = 0; n < 30; ++n) {
-    T x = out[n];
-    x += __shfl_xor(x, 1, 64);
-    x += __shfl_xor(x, 2, 64);
-    out[n] = T(0.25) * x;
-  }
+  for (int n = 0; n < 30; ++n) out[n] = T(0.25) * quad_sum(out[n]);
   if (active) {
 #pragma unroll
     for (int blk = 0; blk < 6; ++blk)
@@ -245,6 +240,18 @@ __global__ __launch_bounds__(FLUX_BLK) void k_flux5(Grid g, const double* __rest
         if ((n & 3) == kgp) st(F + (DIR * 30 + blk * 5 + vg) * N, (uint32_t)cell, out[n]);
       }
   }
+}
+
+// ============================================================================ sampled outputs
+// out[f * n + m] = plane f at cell idx[m], for the nf planes of `planes` (element type S), as double
+template <class S>
+__global__ __launch_bounds__(BLK) void k_gather_cells(long long n, const uint32_t* __restrict__ idx,
+                                                      const S* __restrict__ planes, int nf, long long N,
+                                                      double* __restrict__ out) {
+  const long long m = (long long)blockIdx.x * BLK + threadIdx.x;
+  if (m >= n) return;
+  const uint32_t c = idx[m];
+  for (int f = 0; f < nf; ++f) out[f * n + m] = double(planes[f * N + c]);
 }
 
 // ============================================================================ unit-parity hooks

@@ -1,5 +1,9 @@
-"""Parity at the full size of the Taylor-Green workload (128^3, Re 1600, Ma 0.1) in the launch
-configuration the benchmark times (the same grid, kernels and launch shapes as its steps).
+"""Parity at the full sizes of the workloads, in the launch configurations of their steps:
+- the Taylor-Green vortex (Re 1600, Ma 0.1) at 128^3: the benchmark's grid, kernels and launch
+  shapes;
+- decaying isotropic turbulence (Ma_t 0.5) at 256^3;
+- the Taylor-Green vortex at 512^3 in the FP32-bulk form, the largest single-GPU grid (about 185 GB
+  of device workspace).
 
 The device stage operator is compared with the oracle's stage evaluated at sampled cells only
 (oracle.stage_cells: each cell from its own neighbourhood). The cells are seeded random ones plus
@@ -54,6 +58,65 @@ def test_tgv128_stage_at_sampled_cells(precision):
     for key, a, b in [("L", L, Lo), ("Lt", Lt, Lto), ("sqn", sqn, sqno), ("sqt", sqt, sqto)]:
         e = scaled_err(a[:, cells], b, sc[key])
         assert e <= bar, (key, e)
+
+
+def compare_sampled(case, s, dt, precision, seed):
+    """Device stage at sampled cells (cgks_stage_sampled) against the oracle's per-cell stage on the
+    state the device holds (q, g as stored, so FP32 gradients enter the oracle exactly)."""
+    cells = sampled_cells(case.nx, seed=seed)
+    got = s.stage_sampled(dt, cells)
+    q, g, _, _ = s.get_state()
+    o = oracle.Oracle(oracle.params_from_config(case))
+    o.set_state(q, g)
+    del g
+    ref = o.stage_cells(dt, cells)
+    sc = scales(case, q)
+    bar = 1e-12 if precision == 0 else 100 * 2.0 ** -24
+    for key, a, b in zip(["L", "Lt", "sqn", "sqt"], got, ref):
+        e = scaled_err(a, b, sc[key])
+        assert e <= bar, (key, e)
+
+
+def test_sampled_entry_point_equals_full_stage():
+    from paper_2508_19911_amd import cgks
+    case = inputs.tgv_case(24, ma=0.3).with_(recon=cgks.RECON_NONLINEAR, nx=24, ny=20, nz=18)
+    st = inputs.seeded_smooth_state(case, seed=3, amp=0.1)
+    s = cgks.Solver(case)
+    s.set_state(*st)
+    dt = s.compute_dt(case.cfl)
+    full = s.stage(dt)
+    cells = np.array([0, 5, 777, case.N - 1, 4242, 8191])
+    part = s.stage_sampled(dt, cells)
+    s.close()
+    for a, b in zip(full, part):
+        assert np.array_equal(a[:, cells], b)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_hit256_stage_at_sampled_cells(precision):
+    from paper_2508_19911_amd import cgks
+    case = inputs.hit_case(256).with_(recon=cgks.RECON_NONLINEAR)
+    s = cgks.Solver(case, precision=precision)
+    s.set_state(*inputs.hit_state(case))
+    s.step(1, case.cfl)
+    dt = s.compute_dt(case.cfl)
+    compare_sampled(case, s, dt, precision, seed=1)
+    s.close()
+
+
+def test_tgv512_fp32_stage_at_sampled_cells():
+    from paper_2508_19911_amd import cgks
+    case = inputs.tgv_case(512).with_(recon=cgks.RECON_NONLINEAR)
+    s = cgks.Solver(case, precision=cgks.PREC_FP32_BULK)
+    s.set_ic(cgks.IC_TGV, [case.ma, case.rho0, case.u0])
+    d0 = s.diagnostics()
+    s.step(1, case.cfl)
+    d1 = s.diagnostics()
+    for k in ["mass", "momx", "momy", "momz", "energy"]:
+        assert abs(d1[k] - d0[k]) <= 1e-11 * abs(d0["energy"]), (k, d1[k] - d0[k])
+    dt = s.compute_dt(case.cfl)
+    compare_sampled(case, s, dt, 1, seed=2)
+    s.close()
 
 
 def test_tgv128_fp32_conservation():

@@ -89,3 +89,14 @@ def test_flop_counts_are_current():
     assert fresh == stored
     # the face flux dominates a stage: three launches per stage
     assert 3 * fresh["flux_launch_per_cell"] > 0.8 * fresh["cell_stage_geno"]
+
+
+def test_grid_limit_rejected_before_any_device_work():
+    """Planes are addressed with 32-bit byte offsets: N >= 2^29 is refused by the parameter check."""
+    from paper_2508_19911_amd import cgks, inputs
+    lib = cgks.load()
+    n = ctypes.c_size_t()
+    big = cgks.params_from_case(inputs.tgv_case(8).with_(nx=1024, ny=1024, nz=512))
+    assert lib.cgks_workspace_bytes(ctypes.byref(big), ctypes.byref(n)) == -1
+    ok = cgks.params_from_case(inputs.tgv_case(8).with_(nx=1024, ny=1024, nz=511))
+    assert lib.cgks_workspace_bytes(ctypes.byref(ok), ctypes.byref(n)) == 0 and n.value > 0
