@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # write), from two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE) scaled by a 1 GiB copy
 # kernel: profiles/flux_tgv128_hbm_counters.md.  Valid only for the kernel sources they were taken
 # on; any change to those sources makes the reported traffic null until the counters are retaken.
-FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 2.1517e9,
-                "sources_sha256": "9d8494d6a74f4d91d1e5187c5188cd4c1af0cbb4d9434d40ff652650ecdec8b9"}
+FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 2.1593e9,
+                "sources_sha256": "3af50114d429d9063a7e39336a7ae71024dce88d31befc3bab3512e3def451ed"}
 KERNEL_SOURCES = ["common.hpp", "gks_flux.hpp", "recon.hpp", "recon_tables.hpp", "kernels.hpp"]
 
 

@@ -54,9 +54,11 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // ---------------------------------------------------------------------------- features
-template <class T>
+// The 64 features of one cell, each handed to put(n, value) as soon as it is known (no 64-entry
+// array stays live in registers).
+template <class T, class Put>
 __device__ __forceinline__ void cell_features(const Grid& g, const double* __restrict__ Q,
-                                              const T* __restrict__ G, int cell, float* f) {
+                                              const T* __restrict__ G, int cell, Put&& put) {
   int i, j, k;
   i = cell % g.nx;
   const int jk = cell / g.nx;
@@ -105,9 +107,9 @@ __device__ __forceinline__ void cell_features(const Grid& g, const double* __res
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) f[vi * 27 + d * 9 + m] = float(dv[d][m] * is);
+      for (int m = 0; m < 4; ++m) put(vi * 27 + d * 9 + m, float(dv[d][m] * is));
 #pragma unroll
-      for (int m = 0; m < 5; ++m) f[vi * 27 + d * 9 + 4 + m] = float(gv[d][m] * is);
+      for (int m = 0; m < 5; ++m) put(vi * 27 + d * 9 + 4 + m, float(gv[d][m] * is));
     }
   }
   // features 54..58: per conservative variable, log10 of the largest difference or h dQ on the same
@@ -127,10 +129,10 @@ __device__ __forceinline__ void cell_features(const Grid& g, const double* __res
       }
     }
     // the ratio in FP64, its logarithm in FP32 (a feature needs no more)
-    f[54 + v] = fmaxf(log10f(float(mx / (hmax * sqrt(geno_scale(q5, v))))), -12.0f);
+    put(54 + v, fmaxf(log10f(float(mx / (hmax * sqrt(geno_scale(q5, v))))), -12.0f));
   }
 #pragma unroll
-  for (int n = 59; n < 64; ++n) f[n] = 0.0f;
+  for (int n = 59; n < 64; ++n) put(n, 0.0f);
 }
 
 template <class T>
@@ -138,10 +140,8 @@ __global__ __launch_bounds__(256) void k_features(Grid g, const double* __restri
                                                   const T* __restrict__ G, float* __restrict__ out) {
   const int cell = blockIdx.x * 256 + threadIdx.x;
   if (cell >= g.N) return;
-  float f[64];
-  cell_features<T>(g, Q, G, cell, f);
-#pragma unroll
-  for (int n = 0; n < 64; ++n) out[(long long)cell * 64 + n] = f[n];
+  float* o = out + (long long)cell * 64;
+  cell_features<T>(g, Q, G, cell, [&](int n, float x) { o[n] = x; });
 }
 
 template <class T>
@@ -311,16 +311,12 @@ __global__ __launch_bounds__(256) void k_infer(Grid g, const double* __restrict_
   const int base = blockIdx.x * 256 + w * 64;
   const int cell = base + l;
   {
-    float f[64];
+    uint16_t* row = wl[w].x + l * XS;
     if (cell < g.N)
-      cell_features<T>(g, Q, G, cell, f);
+      cell_features<T>(g, Q, G, cell, [&](int n, float x) { row[n] = f2bf(x); });
     else
 #pragma unroll
-      for (int n = 0; n < 64; ++n) f[n] = 0.0f;
-#pragma unroll
-    for (int n = 0; n < 64; n += 4)
-      *reinterpret_cast<bf16x4*>(wl[w].x + l * XS + n) =
-          bf16x4{(short)f2bf(f[n]), (short)f2bf(f[n + 1]), (short)f2bf(f[n + 2]), (short)f2bf(f[n + 3])};
+      for (int n = 0; n < 64; n += 4) *reinterpret_cast<bf16x4*>(row + n) = bf16x4{0, 0, 0, 0};
   }
   __syncthreads();
   f32x4 acc[4][2];
