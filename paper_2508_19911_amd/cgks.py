@@ -68,6 +68,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2508_19911_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded, the one that owns the
+    # streams and the device memory it is handed (loaded the other way round, a second runtime comes
+    # up that does not see the device)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P, I, D, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     pp = ctypes.POINTER(Params)
