@@ -169,6 +169,13 @@ def test_device_initial_condition_matches_inputs():
     qg, gg, _, _ = s.get_state()
     assert np.abs(qg - q).max() <= 1e-12 * np.abs(q).max()
     assert np.abs(gg - g).max() <= 1e-11 * max(np.abs(g).max(), 1.0)
+    cs = inputs.tgv_case(10, ma=2.0, supersonic=True)
+    qs, gs = inputs.tgv_state(cs)
+    ss = cg().Solver(cs)
+    ss.set_ic(cg().IC_TGV_SUPERSONIC, [2.0])
+    qg, gg, _, _ = ss.get_state()
+    assert np.abs(qg - qs).max() <= 1e-12 * np.abs(qs).max()
+    assert np.abs(gg - gs).max() <= 1e-11 * max(np.abs(gs).max(), 1.0)
     cv = inputs.vortex_case(16)
     qv, gv = inputs.vortex_state(cv)
     sv = cg().Solver(cv)
