@@ -138,15 +138,22 @@ struct TimedScope {
   Ctx& c;
   int cls;
   hipEvent_t a = nullptr;
+  // a record that fails drops this measurement (timing is diagnostic; the launches are unaffected)
   TimedScope(Ctx& ctx, int k) : c(ctx), cls(k) {
-    if (c.tm.on && (a = timing_event(c))) hipEventRecord(a, c.stream);
+    if (c.tm.on && (a = timing_event(c)) && hipEventRecord(a, c.stream) != hipSuccess) {
+      c.tm.pool.push_back(a);
+      a = nullptr;
+    }
   }
   ~TimedScope() {
     if (!a) return;
     hipEvent_t b = timing_event(c);
-    if (!b) return;
-    hipEventRecord(b, c.stream);
-    c.tm.recs.push_back({cls, a, b});
+    if (b && hipEventRecord(b, c.stream) == hipSuccess) {
+      c.tm.recs.push_back({cls, a, b});
+      return;
+    }
+    c.tm.pool.push_back(a);
+    if (b) c.tm.pool.push_back(b);
   }
 };
 
@@ -337,14 +344,15 @@ int cgks_create(const cgks_params* p, void* ws, size_t bytes, void* stream, void
 int cgks_destroy(void* ctx) {
   Ctx* c = static_cast<Ctx*>(ctx);
   if (!c) return CGKS_OK;
-  hipStreamSynchronize(c->stream);
+  // the caller's workspace must not be released while work of this context is in flight
+  const hipError_t sync = hipStreamSynchronize(c->stream);
   for (auto& r : c->tm.recs) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
-  for (auto e : c->tm.pool) hipEventDestroy(e);
+  for (auto e : c->tm.pool) (void)hipEventDestroy(e);
   delete c;
-  return CGKS_OK;
+  return sync == hipSuccess ? CGKS_OK : dev_error("hipStreamSynchronize", sync);
 }
 
 int cgks_timing_enable(void* ctx, int on) {

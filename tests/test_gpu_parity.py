@@ -225,3 +225,35 @@ def test_conservation_fp32_bulk():
     d1 = s.diagnostics()
     for k in ["mass", "momx", "momy", "momz", "energy"]:
         assert abs(d1[k] - d0[k]) <= 1e-12 * abs(d0["energy"]), (k, d1[k] - d0[k])
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 1), (3, 2, 1), (1, 5, 1)])
+@pytest.mark.parametrize("recon", [0, 1])
+def test_degenerate_grids(dims, recon):
+    """Grids of one to six cells: every stencil neighbour wraps onto the cell itself or its twin, and
+    the 16-cell blocks of the coefficients and faces are almost empty. Stage operator and two steps
+    against the oracle at the FP64 bar."""
+    case = inputs.tgv_case(4, ma=0.3).with_(nx=dims[0], ny=dims[1], nz=dims[2], lx=1.3, ly=1.1, lz=0.7,
+                                            recon=recon)
+    st = inputs.seeded_smooth_state(case, seed=13, amp=0.1)
+    o, s = pair(case, st)
+    dt = o.compute_dt(0.3)
+    sc = scales(case, st[0])
+    for key, a, b in zip(["L", "Lt", "sqn", "sqt"], s.stage(dt), o.stage(dt)):
+        assert scaled_err(a, b, sc[key]) <= 1e-12, key
+    o.step_fixed(2, dt); s.step_fixed(2, dt)
+    assert scaled_err(s.get_state()[0], o.get_state()[0], sc["Q"]) <= 2e-12
+
+
+def test_sampled_stage_rejects_bad_cell_lists():
+    case = inputs.tgv_case(6, ma=0.3)
+    s = cg().Solver(case)
+    s.set_state(*inputs.seeded_smooth_state(case, seed=2, amp=0.1))
+    dt = s.compute_dt(0.3)
+    for cells in ([], [case.N], [-1], [0, case.N + 5]):
+        with pytest.raises(cg().CgksError) as e:
+            s.stage_sampled(dt, np.array(cells, dtype=np.int64))
+        assert e.value.code == -1
+    with pytest.raises(cg().CgksError):
+        s.stage_sampled(-1.0, np.array([0]))
+    s.close()
