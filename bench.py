@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # write), from two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE) scaled by a 1 GiB copy
 # kernel: profiles/flux_tgv128_hbm_counters.md.  Valid only for the kernel sources they were taken
 # on; any change to those sources makes the reported traffic null until the counters are retaken.
-FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 2.1593e9,
-                "sources_sha256": "3af50114d429d9063a7e39336a7ae71024dce88d31befc3bab3512e3def451ed"}
+FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8769e9,
+                "sources_sha256": "97d7cecc0c004d71ca222ebad75a5e623b098195fefbdea051776120ece34dc6"}
 KERNEL_SOURCES = ["common.hpp", "gks_flux.hpp", "recon.hpp", "recon_tables.hpp", "kernels.hpp"]
 
 

@@ -128,6 +128,16 @@ __device__ __forceinline__ T quad_sum(T x) {
   return x + quad_perm<QUAD_XOR2>(x);
 }
 
+// XCD-aware block order.  Workgroups are handed to the 8 XCDs round robin (block b runs on XCD b mod
+// 8), and each XCD has its own L2.  The remap gives every XCD a contiguous range of logical blocks, so
+// neighbouring blocks (which share halo data) run on the same L2.  A bijection on [0, nb).
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned nb) {
+  const unsigned q = nb / NUM_XCD, r = nb % NUM_XCD;
+  const unsigned x = b % NUM_XCD, i = b / NUM_XCD;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 // face-frame permutation: the face of axis d sees (normal, t1, t2) = axes (d, d+1, d+2) mod 3
 __host__ __device__ constexpr int perm(int d, int k) { return (d + k) % 3; }
 

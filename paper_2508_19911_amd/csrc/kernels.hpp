@@ -178,7 +178,12 @@ __global__ __launch_bounds__(FLUX_BLK) void k_flux5(Grid g, const double* __rest
   using V = typename Vec16<T>::type;
   const int kgp = threadIdx.x & 3;
   const int fl = threadIdx.x >> 2;
-  int cell = blockIdx.x * FLUX_FACES + fl;
+  // x faces: the low neighbour of a block's first cell lies in the previous block, so contiguous
+  // block ranges per XCD keep it in the same L2.  y and z faces keep the hardware's round-robin
+  // order: their neighbour blocks (nx/16 and nx ny/16 blocks back) are then on the same XCD and only
+  // 1/8 as far back in its order, inside the L2.
+  const unsigned blk = DIR == 0 ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  int cell = (int)blk * FLUX_FACES + fl;
   const bool active = cell < g.N;
   if (!active) cell = (int)g.N - 1;  // keep the lane in the reduction; its result is not stored
   int i, j, k;
