@@ -64,6 +64,7 @@ def lib():
         L.cgkso_stencil_offsets.argtypes = [P]
         L.cgkso_recon_cell.argtypes = [ctypes.POINTER(Params), P, P, P, D, I, P, P]
         L.cgkso_face_gauss_points.argtypes = [P]
+        L.cgkso_chi_deviation.argtypes = [ctypes.c_void_p, P]
         L.cgkso_stage_cells.argtypes = [ctypes.c_void_p, D, P, ctypes.c_long, P, P, P, P]
         L.cgkso_geno_scale.argtypes = [P, I]
         L.cgkso_geno_scale.restype = D
@@ -180,6 +181,14 @@ class Oracle:
     def features(self):
         out = np.empty((self.N, 64), dtype=np.float32)
         rc = lib().cgkso_features(self.h, _ptr(out))
+        if rc != 0:
+            raise RuntimeError(rc)
+        return out
+
+    def chi_deviation(self):
+        """max over the 5 variables of |1 - chi| under full GENO, per cell (what labels() thresholds)."""
+        out = np.empty(self.N)
+        rc = lib().cgkso_chi_deviation(self.h, _ptr(out))
         if rc != 0:
             raise RuntimeError(rc)
         return out

@@ -110,6 +110,8 @@ int  cgkso_indicator_set(void* ctx, const float* params, size_t n, double logit_
 int  cgkso_features(void* ctx, float* out);
 /* GENO labels of every cell of the stored state: 1 iff max_v |1 - chi_v| > thr. */
 int  cgkso_labels(void* ctx, double thr, unsigned char* out);
+/* The quantity the labels threshold: max over the 5 variables of |1 - chi| under full GENO, per cell. */
+int  cgkso_chi_deviation(void* ctx, double* dev);
 /* Forward pass on n samples x[n][64]: logits[n].  bf16 != 0 rounds inputs, weights and hidden
  * activations to bfloat16 (round to nearest even) as the GPU kernels do. */
 void cgkso_mlp_forward(const float* params, const float* x, long n, int bf16, double* logits);

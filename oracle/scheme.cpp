@@ -604,7 +604,19 @@ int cgkso_features(void* ctx, float* out) {
   return CGKSO_OK;
 }
 
+int cgkso_chi_deviation(void* ctx, double* dev);
+
 int cgkso_labels(void* ctx, double thr, unsigned char* out) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c->have_state) return CGKSO_ESTATE;
+  std::vector<double> dev(c->N);
+  const int rc = cgkso_chi_deviation(ctx, dev.data());
+  if (rc) return rc;
+  for (long n = 0; n < c->N; ++n) out[n] = dev[n] > thr ? 1 : 0;
+  return CGKSO_OK;
+}
+
+int cgkso_chi_deviation(void* ctx, double* dev) {
   Ctx* c = static_cast<Ctx*>(ctx);
   if (!c->have_state) return CGKSO_ESTATE;
   const cgkso_params& P = c->P;
@@ -629,7 +641,7 @@ int cgkso_labels(void* ctx, double thr, unsigned char* out) {
           recon_cell(P, q, g, c->h, geno_scale(q5, v), 1, o, info);
           worst = std::fmax(worst, std::fabs(1.0 - info[0]));
         }
-        out[ci] = worst > thr ? 1 : 0;
+        dev[ci] = worst;
       }
   return CGKSO_OK;
 }

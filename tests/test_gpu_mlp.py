@@ -118,8 +118,15 @@ def test_labels_match_oracle(precision):
     s = cg().Solver(case, precision=precision); s.set_state(q, g)
     lo = o.labels(0.01); lg = s.labels(0.01)
     assert 0 < lo.sum() < case.N
-    mism = np.mean(lo != lg)
-    assert mism == 0.0 if precision == 0 else mism < 0.02, mism
+    if precision == 0:
+        assert np.array_equal(lo, lg)  # the same FP64 chi on both sides
+    else:
+        # the device decides in FP32: identical wherever the FP64 deviation |1 - chi| is farther from
+        # the threshold than float rounding of chi can move it
+        dev = o.chi_deviation()
+        clear = np.abs(dev - 0.01) > 1e-4
+        assert clear.mean() > 0.9
+        assert np.array_equal(lo[clear], lg[clear])
 
 
 def test_learned_stage_matches_oracle():
