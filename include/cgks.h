@@ -35,7 +35,7 @@ extern "C" {
 
 enum {
   CGKS_OK = 0,
-  CGKS_EINVAL = -1,        /* bad size, parameter or enum */
+  CGKS_EINVAL = -1,        /* bad size, parameter or enum, or a NULL context */
   CGKS_EWORKSPACE = -2,    /* workspace missing, too small or misaligned */
   CGKS_EDEVICE = -3,       /* a HIP call failed (message kept for cgks_strerror) */
   CGKS_ENONPHYSICAL = -4,  /* rho <= 0, p <= 0 or NaN found at the start of a step */

@@ -356,12 +356,14 @@ int cgks_destroy(void* ctx) {
 }
 
 int cgks_timing_enable(void* ctx, int on) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   c.tm.on = on != 0;
   return CGKS_OK;
 }
 
 int cgks_timing_read(void* ctx, long* count, double* ms, int nclasses) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!count || !ms || nclasses < 1) return CGKS_EINVAL;
   for (int k = 0; k < nclasses; ++k) {
@@ -384,6 +386,7 @@ int cgks_timing_read(void* ctx, long* count, double* ms, int nclasses) {
 }
 
 int cgks_set_state(void* ctx, const double* q, const double* g, double t, long step) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!q) return CGKS_EINVAL;
   const size_t N = c.g.N;
@@ -413,6 +416,7 @@ int cgks_set_state(void* ctx, const double* q, const double* g, double t, long s
 }
 
 int cgks_set_ic(void* ctx, int kind, const double* prm, int nprm) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   ICParams ip;
   ip.kind = kind;
@@ -444,6 +448,7 @@ int cgks_set_ic(void* ctx, int kind, const double* prm, int nprm) {
 }
 
 int cgks_get_state(void* ctx, double* q, double* g, double* t, long* step) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_state) return CGKS_ESTATE;
   const size_t N = c.g.N;
@@ -466,6 +471,7 @@ int cgks_get_state(void* ctx, double* q, double* g, double* t, long* step) {
 }
 
 int cgks_compute_dt(void* ctx, double cfl, double* dt) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_state) return CGKS_ESTATE;
   if (!(cfl > 0.0) || !dt) return CGKS_EINVAL;
@@ -478,6 +484,7 @@ int cgks_compute_dt(void* ctx, double cfl, double* dt) {
 }
 
 int cgks_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done, double* t_now) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   int done = 0, rc = CGKS_OK;
   if (!c.have_state) rc = CGKS_ESTATE;
@@ -509,6 +516,7 @@ int cgks_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done,
 }
 
 int cgks_step_fixed(void* ctx, int nsteps, double dt) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_state) return CGKS_ESTATE;
   if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) return CGKS_ESTATE;
@@ -524,6 +532,7 @@ int cgks_step_fixed(void* ctx, int nsteps, double dt) {
 }
 
 int cgks_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double* sqt) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_state) return CGKS_ESTATE;
   if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) return CGKS_ESTATE;
@@ -564,6 +573,7 @@ int cgks_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double*
 
 int cgks_stage_sampled(void* ctx, double dt, const long* cells, long n, double* L, double* Lt,
                        double* sqn, double* sqt) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_state) return CGKS_ESTATE;
   if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) return CGKS_ESTATE;
@@ -616,6 +626,7 @@ int cgks_stage_sampled(void* ctx, double dt, const long* cells, long n, double* 
 }
 
 int cgks_diagnostics(void* ctx, double rho0, double u0, cgks_diag* out) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_state) return CGKS_ESTATE;
   if (!out) return CGKS_EINVAL;
@@ -660,6 +671,7 @@ int cgks_diagnostics(void* ctx, double rho0, double u0, cgks_diag* out) {
 }
 
 int cgks_get_flags(void* ctx, unsigned char* flags) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!flags) return CGKS_EINVAL;
   HIPCK(hipMemcpyAsync(flags, c.ws + c.L.flags, c.g.N, hipMemcpyDeviceToHost, c.stream));
@@ -669,6 +681,7 @@ int cgks_get_flags(void* ctx, unsigned char* flags) {
 
 // ---------------------------------------------------------------------------- indicator
 int cgks_indicator_set(void* ctx, const float* params, size_t n, double logit_threshold) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!params || n != (size_t)mlp::NPARAM) return CGKS_EINVAL;
   c.mlp_host.assign(params, params + n);
@@ -680,6 +693,7 @@ int cgks_indicator_set(void* ctx, const float* params, size_t n, double logit_th
 }
 
 int cgks_indicator_get(void* ctx, float* params, size_t n) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!params || n != (size_t)mlp::NPARAM) return CGKS_EINVAL;
   if (!c.have_mlp) return CGKS_ESTATE;
@@ -689,6 +703,7 @@ int cgks_indicator_get(void* ctx, float* params, size_t n) {
 }
 
 int cgks_features(void* ctx, float* out) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_state) return CGKS_ESTATE;
   if (!out || c.p.scheme != CGKS_SCHEME_CGKS5) return CGKS_EINVAL;
@@ -705,6 +720,7 @@ int cgks_features(void* ctx, float* out) {
 }
 
 int cgks_indicator_logits(void* ctx, float* out) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_state || !c.have_mlp) return CGKS_ESTATE;
   if (!out || c.p.scheme != CGKS_SCHEME_CGKS5) return CGKS_EINVAL;
@@ -725,6 +741,7 @@ int cgks_indicator_logits(void* ctx, float* out) {
 }
 
 int cgks_labels(void* ctx, double thr, unsigned char* out) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_state) return CGKS_ESTATE;
   if (!out || c.p.scheme != CGKS_SCHEME_CGKS5) return CGKS_EINVAL;
@@ -742,6 +759,7 @@ int cgks_labels(void* ctx, double thr, unsigned char* out) {
 
 int cgks_indicator_train(void* ctx, const void* dev_x, const void* dev_y, long n, int epochs,
                          double lr, uint64_t seed, double* final_loss) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_mlp) return CGKS_ESTATE;
   if (!dev_x || !dev_y || n < 1 || epochs < 0 || !(lr > 0.0)) return CGKS_EINVAL;
@@ -758,6 +776,7 @@ int cgks_indicator_train(void* ctx, const void* dev_x, const void* dev_y, long n
 
 int cgks_indicator_grad(void* ctx, const void* dev_x, const void* dev_y, long n, double* loss,
                         double* grad) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_mlp) return CGKS_ESTATE;
   if (!dev_x || !dev_y || n < 1 || !grad) return CGKS_EINVAL;
@@ -766,6 +785,7 @@ int cgks_indicator_grad(void* ctx, const void* dev_x, const void* dev_y, long n,
 }
 
 int cgks_debug_point_flux(void* ctx, double dt, long n, const double* wl, const double* wr, double* out) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (n < 1 || !wl || !wr || !out || !(dt > 0.0)) return CGKS_EINVAL;
   const size_t cap = (c.p.scheme == CGKS_SCHEME_CGKS5 ? 90 : 30) * (size_t)c.g.N *
@@ -810,6 +830,7 @@ int copy_coefficients(Ctx& c, double* out) {
 extern "C" {
 
 int cgks_debug_coefficients(void* ctx, double* out) {
+  if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (!c.have_state) return CGKS_ESTATE;
   if (!out || c.p.scheme != CGKS_SCHEME_CGKS5) return CGKS_EINVAL;

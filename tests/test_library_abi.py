@@ -100,3 +100,17 @@ def test_grid_limit_rejected_before_any_device_work():
     assert lib.cgks_workspace_bytes(ctypes.byref(big), ctypes.byref(n)) == -1
     ok = cgks.params_from_case(inputs.tgv_case(8).with_(nx=1024, ny=1024, nz=511))
     assert lib.cgks_workspace_bytes(ctypes.byref(ok), ctypes.byref(n)) == 0 and n.value > 0
+
+
+def test_null_context_is_rejected_without_device_work():
+    """Every entry point taking a context returns EINVAL for NULL (checked before any HIP call)."""
+    from paper_2508_19911_amd import cgks
+    lib = cgks.load()
+    z = ctypes.c_void_p(None)
+    d = ctypes.c_double()
+    assert lib.cgks_compute_dt(z, 0.5, ctypes.byref(d)) == -1
+    assert lib.cgks_step_fixed(z, 1, 0.1) == -1
+    assert lib.cgks_stage(z, 0.1, None, None, None, None) == -1
+    assert lib.cgks_set_ic(z, 1, None, 0) == -1
+    assert lib.cgks_get_flags(z, None) == -1
+    assert lib.cgks_destroy(z) == 0  # destroying nothing is a no-op
