@@ -129,6 +129,23 @@ def test_gks2_fp64(recon):
     assert field_err(s.get_state()[0], o.get_state()[0]) <= 1e-12
 
 
+@pytest.mark.parametrize("recon", [0, 1])
+def test_gks2_fp32_bulk(recon):
+    """GKS-2nd in the FP32-bulk form: slopes and flux in float, accumulation in FP64; the bar of the
+    FP32 form (O(100) float roundings at the natural scales)."""
+    case, st = make_state("ragged_viscous")
+    case = case.with_(scheme=1, recon=recon)
+    o, s = pair(case, st, precision=1)
+    dt = o.compute_dt(0.5)
+    Lo, Lto, _, _ = o.stage(dt)
+    Lg, Ltg, _, _ = s.stage(dt)
+    sc = scales(case, st[0])
+    eps32 = 2.0 ** -24
+    assert scaled_err(Lg, Lo, sc["L"]) <= 100 * eps32 and scaled_err(Ltg, Lto, sc["Lt"]) <= 100 * eps32
+    o.step(5, 0.5); s.step(5, 0.5)
+    assert scaled_err(s.get_state()[0], o.get_state()[0], sc["Q"]) <= 10 * eps32
+
+
 def test_diagnostics_fp64():
     case, st = make_state("tgv8")
     case = case.with_(recon=1)
