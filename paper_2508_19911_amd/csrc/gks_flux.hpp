@@ -24,26 +24,36 @@
 
 namespace cgks {
 
-// Moments of a normalised Maxwellian: <u^k> (the half range for the l/r sides), <v^k>, <w^k>,
-// <xi^2>, <xi^4>.
-template <class T>
-struct Mom {
-  T u[7];
-  T v[6];
-  T w[6];
-  T xi2, xi4;
-};
-
 // primitive state of a Maxwellian; var = 1/(2 lam) = p/rho is kept beside lam
 template <class T>
 struct Prim {
   T rho, U, V, W, lam, var;
 };
 
-// velocity moments by the Gaussian recursion <x^{k}> = X <x^{k-1}> + (k-1)/(2 lam) <x^{k-2}>
-// (exact for a half range bounded at 0 once k >= 2); HALF = +1 (u > 0), -1 (u < 0) or 0 (full)
+// Moment products in a tangentially co-moving frame.
+//
+// Seen from the frame that moves with a Maxwellian's tangential velocity (V, W), its normal velocity
+// u keeps the mean U (the half-space split is at u = 0 in either frame) while v, w and xi are
+// centred.  Every moment odd in v or w then vanishes, and the products <u^A (s.psi) psi> and
+// <u^A v (s.psi) psi> of a slope polynomial s = s0 + s1 u + s2 v + s3 w + s4 psi4 need only these
+// sums over the normal moments u_k = <u^k> (half or full range):
+//   vu[k] = <u^k v^2>     = var u_k
+//   ph[k] = <u^k psi4>    = (u_{k+2} + r1 u_k) / 2
+//   qq[k] = <u^k psi4^2>  = (u_{k+4} + 2 r1 u_{k+2} + r2 u_k) / 4
+//   vh[k] = <u^k v^2 psi4> = (vu_{k+2} + (K+4) var vu_k) / 2
+// with psi4 = (u^2 + r)/2, r = v^2 + w^2 + xi^2, r1 = <r> = (K+2) var and
+// r2 = <r^2> = (K+2)(K+4) var^2 (K internal degrees of freedom, <xi^2> = K var,
+// <xi^4> = K (K+2) var^2).  Moment vectors computed here are of psi' = (1, u, v', w', psi4') in the
+// frame; from_frame / to_frame carry them to and from the lab.
+template <class T>
+struct FrameMom {
+  T u[7], vu[4], ph[4], qq[3], vh[2];
+};
+
+// normal moments by the Gaussian recursion u_k = U u_{k-1} + (k-1) var u_{k-2} (exact on a half
+// range bounded at 0 once k >= 2); HALF = +1 (u > 0), -1 (u < 0) or 0 (full range)
 template <int HALF, class T>
-__host__ __device__ __forceinline__ void maxwell_moments(const Prim<T>& p, T Kdof, Mom<T>& m) {
+__host__ __device__ __forceinline__ void frame_moments(const Prim<T>& p, T Kdof, FrameMom<T>& m) {
   const T var = p.var;
   if constexpr (HALF == 0) {
     m.u[0] = T(1);
@@ -62,81 +72,126 @@ __host__ __device__ __forceinline__ void maxwell_moments(const Prim<T>& p, T Kdo
   }
 #pragma unroll
   for (int k = 2; k < 7; ++k) m.u[k] = p.U * m.u[k - 1] + T(k - 1) * var * m.u[k - 2];
-  m.v[0] = T(1);
-  m.v[1] = p.V;
-  m.w[0] = T(1);
-  m.w[1] = p.W;
+  const T hr1 = T(0.5) * (Kdof + T(2)) * var;
+  const T qr2 = T(0.25) * (Kdof + T(2)) * (Kdof + T(4)) * var * var;
+  const T hk4 = T(0.5) * (Kdof + T(4)) * var;
 #pragma unroll
-  for (int k = 2; k < 6; ++k) {
-    m.v[k] = p.V * m.v[k - 1] + T(k - 1) * var * m.v[k - 2];
-    m.w[k] = p.W * m.w[k - 1] + T(k - 1) * var * m.w[k - 2];
-  }
-  m.xi2 = Kdof * var;
-  m.xi4 = Kdof * (Kdof + T(2)) * var * var;
-}
-
-// <u^A v^B w^C psi>, psi = (1, u, v, w, (u^2+v^2+w^2+xi^2)/2).  Products are formed as
-// <u^A> (<v^B> <w^C>): the tangential pairs are few and shared by every normal order A.
-template <int A, int B, int C, class T>
-__host__ __device__ __forceinline__ void mvec(const Mom<T>& m, T o[5]) {
-  const T vw = m.v[B] * m.w[C];
-  const T b = m.u[A] * vw;
-  o[0] = b;
-  o[1] = m.u[A + 1] * vw;
-  o[2] = m.u[A] * (m.v[B + 1] * m.w[C]);
-  o[3] = m.u[A] * (m.v[B] * m.w[C + 1]);
-  o[4] = T(0.5) * (m.u[A + 2] * vw + m.u[A] * (m.v[B + 2] * m.w[C]) + m.u[A] * (m.v[B] * m.w[C + 2]) +
-                   b * m.xi2);
-}
-
-// <xi^2 u^A v^B w^C psi>
-template <int A, int B, int C, class T>
-__host__ __device__ __forceinline__ void mvec_xi(const Mom<T>& m, T o[5]) {
-  T t[5];
-  mvec<A, B, C>(m, t);
-  const T b = t[0];
+  for (int k = 0; k < 4; ++k) m.vu[k] = var * m.u[k];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) o[i] = m.xi2 * t[i];
-  // <xi^2 psi_4> = (xi2 <(u^2+v^2+w^2) ...> + xi4 <...>)/2 = xi2 (t4 - b xi2/2) + xi4 b/2
-  o[4] = m.xi2 * (t[4] - T(0.5) * b * m.xi2) + T(0.5) * m.xi4 * b;
-}
-
-// <s u^A v^B w^C psi> for the slope polynomial s = s1 + s2 u + s3 v + s4 w + s5 (u^2+v^2+w^2+xi^2)/2;
-// accumulated into o with weight wgt
-template <int A, int B, int C, class T>
-__host__ __device__ __forceinline__ void smom_acc(const Mom<T>& m, const T s[5], T wgt, T o[5]) {
-  T t0[5], t1[5], t2[5], t3[5], tu[5], tv[5], tw[5], tx[5];
-  mvec<A, B, C>(m, t0);
-  mvec<A + 1, B, C>(m, t1);
-  mvec<A, B + 1, C>(m, t2);
-  mvec<A, B, C + 1>(m, t3);
-  mvec<A + 2, B, C>(m, tu);
-  mvec<A, B + 2, C>(m, tv);
-  mvec<A, B, C + 2>(m, tw);
-  mvec_xi<A, B, C>(m, tx);
-  const T h5 = T(0.5) * s[4];
+  for (int k = 0; k < 4; ++k) m.ph[k] = T(0.5) * m.u[k + 2] + hr1 * m.u[k];
 #pragma unroll
-  for (int i = 0; i < 5; ++i)
-    o[i] += wgt * (s[0] * t0[i] + s[1] * t1[i] + s[2] * t2[i] + s[3] * t3[i] +
-                   h5 * (tu[i] + tv[i] + tw[i] + tx[i]));
+  for (int k = 0; k < 3; ++k) m.qq[k] = T(0.25) * m.u[k + 4] + hr1 * m.u[k + 2] + qr2 * m.u[k];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) m.vh[k] = T(0.5) * m.vu[k + 2] + hk4 * m.vu[k];
 }
 
-// Closed-form micro-slope solver: the polynomial a with <a psi> = R for a Maxwellian.
-// ik3 = 1/(K+3).
+// o = x (SET) or o + x
+template <bool SET, class T>
+__host__ __device__ __forceinline__ T first(T o, T a, T b) {
+  if constexpr (SET)
+    return a * b;
+  else
+    return o + a * b;
+}
+
+// o (=|+=) <u^A (s.psi') psi'>
+template <int A, bool SET = false, class T>
+__host__ __device__ __forceinline__ void tslope(const FrameMom<T>& m, const T s[5], T o[5]) {
+  o[0] = first<SET>(o[0], s[0], m.u[A]);
+  o[0] = o[0] + s[1] * m.u[A + 1];
+  o[0] = o[0] + s[4] * m.ph[A];
+  o[1] = first<SET>(o[1], s[0], m.u[A + 1]);
+  o[1] = o[1] + s[1] * m.u[A + 2];
+  o[1] = o[1] + s[4] * m.ph[A + 1];
+  o[2] = first<SET>(o[2], s[2], m.vu[A]);
+  o[3] = first<SET>(o[3], s[3], m.vu[A]);
+  o[4] = first<SET>(o[4], s[0], m.ph[A]);
+  o[4] = o[4] + s[1] * m.ph[A + 1];
+  o[4] = o[4] + s[4] * m.qq[A];
+}
+
+// o += <u^A t (s.psi') psi'> for a tangential velocity t = v' (AX = 2) or w' (AX = 3)
+template <int A, int AX, class T>
+__host__ __device__ __forceinline__ void tslope_t(const FrameMom<T>& m, const T s[5], T o[5]) {
+  o[0] = o[0] + s[AX] * m.vu[A];
+  o[1] = o[1] + s[AX] * m.vu[A + 1];
+  o[AX] = o[AX] + s[0] * m.vu[A];
+  o[AX] = o[AX] + s[1] * m.vu[A + 1];
+  o[AX] = o[AX] + s[4] * m.vh[A];
+  o[4] = o[4] + s[AX] * m.vh[A];
+}
+
+// o (=|+=) rho <u^A psi'> = rho (u_A, u_{A+1}, 0, 0, ph_A)
+template <int A, class T>
+__host__ __device__ __forceinline__ void tpsi(const FrameMom<T>& m, T rho, T o[5]) {
+  o[0] = rho * m.u[A];
+  o[1] = rho * m.u[A + 1];
+  o[2] = T(0);
+  o[3] = T(0);
+  o[4] = rho * m.ph[A];
+}
+
+// Galilean shift by the tangential velocity (V, W), kv = (V^2 + W^2)/2:
+// lab moments R -> frame moments R' (psi4 = psi4' + V v' + W w' + kv)
 template <class T>
-__host__ __device__ __forceinline__ void micro_slope(const Prim<T>& p, T Kdof, T ik3, const T R[5],
-                                                     T a[5]) {
-  const T Ad = R[1] - p.U * R[0];
-  const T Cd = R[2] - p.V * R[0];
-  const T Dd = R[3] - p.W * R[0];
-  const T q = p.U * p.U + p.V * p.V + p.W * p.W + (Kdof + T(3)) * p.var;
-  const T Bd = T(2) * R[4] - q * R[0];
-  a[4] = T(4) * p.lam * p.lam * (Bd - T(2) * (p.U * Ad + p.V * Cd + p.W * Dd)) * ik3;
-  a[1] = T(2) * p.lam * Ad - p.U * a[4];
-  a[2] = T(2) * p.lam * Cd - p.V * a[4];
-  a[3] = T(2) * p.lam * Dd - p.W * a[4];
-  a[0] = R[0] - p.U * a[1] - p.V * a[2] - p.W * a[3] - T(0.5) * a[4] * q;
+__host__ __device__ __forceinline__ void to_frame(const T* R, T V, T W, T kv, T o[5]) {
+  o[0] = R[0];
+  o[1] = R[1];
+  o[2] = R[2] - V * R[0];
+  o[3] = R[3] - W * R[0];
+  o[4] = R[4] - V * R[2] - W * R[3] + kv * R[0];
 }
+// frame moments o' -> lab, stored (SET) or added into L; ZT: o'[2] = o'[3] = 0
+template <bool SET, bool ZT = false, class T>
+__host__ __device__ __forceinline__ void from_frame(const T o[5], T V, T W, T kv, T L[5]) {
+  if constexpr (SET) {
+    L[0] = o[0];
+    L[1] = o[1];
+    if constexpr (ZT) {
+      L[2] = V * o[0];
+      L[3] = W * o[0];
+      L[4] = o[4] + kv * o[0];
+    } else {
+      L[2] = o[2] + V * o[0];
+      L[3] = o[3] + W * o[0];
+      L[4] = o[4] + V * o[2] + W * o[3] + kv * o[0];
+    }
+  } else {
+    L[0] = L[0] + o[0];
+    L[1] = L[1] + o[1];
+    if constexpr (ZT) {
+      L[2] = L[2] + V * o[0];
+      L[3] = L[3] + W * o[0];
+      L[4] = L[4] + o[4] + kv * o[0];
+    } else {
+      L[2] = L[2] + o[2] + V * o[0];
+      L[3] = L[3] + o[3] + W * o[0];
+      L[4] = L[4] + o[4] + V * o[2] + W * o[3] + kv * o[0];
+    }
+  }
+}
+
+// Micro-slope solver in the frame (tangential means zero): the polynomial a with <a psi'> = R for the
+// full-range Maxwellian.  Closed form of the 5x5 moment system; uniform per Maxwellian:
+// tl = 2 lam, c4 = 8 lam^2 / (K+3), hq = (U^2 + (K+3) var)/2.
+template <class T>
+struct SlopeSolver {
+  T U, tl, c4, hq;
+  __host__ __device__ __forceinline__ void init(const Prim<T>& p, T Kdof, T ik3) {
+    U = p.U;
+    tl = T(2) * p.lam;
+    c4 = T(8) * p.lam * p.lam * ik3;
+    hq = T(0.5) * (p.U * p.U + (Kdof + T(3)) * p.var);
+  }
+  __host__ __device__ __forceinline__ void solve(const T R[5], T a[5]) const {
+    const T Ad = R[1] - U * R[0];
+    a[4] = c4 * (R[4] - hq * R[0] - U * Ad);
+    a[1] = tl * Ad - U * a[4];
+    a[2] = tl * R[2];
+    a[3] = tl * R[3];
+    a[0] = R[0] - U * a[1] - hq * a[4];
+  }
+};
 
 struct FluxParams {
   double gamma;
@@ -176,6 +231,11 @@ __host__ __device__ __forceinline__ T viscosity(const FluxParams& P, T Temp) {
 // Interface flux at one point in the face frame (first axis = face normal).
 // WL/WR: conservative values (FP64); DL/DR[d*5+v]: derivative of variable v along face-frame axis d.
 // out: Fn[5], Ft[5], QLn[5], QLt[5], QRn[5], QRt[5].  NOUT = 10 skips the interface values.
+//
+// Each Maxwellian (the two sides, then g0) is handled in its own tangentially co-moving frame, where
+// the moment products are sparse; the results are shifted back to the lab before they are summed.
+// Slopes are solved from the density-weighted derivatives directly (b = rho a), so every piece comes
+// out density-weighted without a division.
 template <class T, int NOUT>
 __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt, const double* WL,
                                          const T* DL, const double* WR, const T* DR, T* out) {
@@ -203,72 +263,97 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
     }
   }
 
-  T W0[5] = {0, 0, 0, 0, 0};
-  T dW0[3][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
-  T SP[6][5];  // sums over the sides of rho_s x {<u psi>, <u (a.u) psi>, <u A psi>, <psi>, <(a.u) psi>, <A psi>}
+  // lab sums over the two sides, each piece density-weighted on its half space:
+  // W0 = <psi>, dW0[d] = <a_d psi>, SP = {<u psi>, <u (a.u) psi>, <u A psi>, -, <(a.u) psi>, <A psi>}
+  T W0[5], dW0[3][5], SP[6][5];
   T eul[2][5];
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int v = 0; v < 5; ++v) SP[i][v] = T(0);
-
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const Prim<T>& p = pr[s];
     const T* D = s ? DR : DL;
-    Mom<T> mh, mf;
+    const T V = p.V, W = p.W, kv = T(0.5) * (V * V + W * W);
+    FrameMom<T> mh, mf;
     if (s == 0)
-      maxwell_moments<+1>(p, K, mh);
+      frame_moments<+1>(p, K, mh);
     else
-      maxwell_moments<-1>(p, K, mh);
-    maxwell_moments<0>(p, K, mf);
-    const T irho = drcp(p.rho);
-    T a[3][5];
+      frame_moments<-1>(p, K, mh);
+    frame_moments<0>(p, K, mf);
+    SlopeSolver<T> sv;
+    sv.init(p, K, ik3);
+    // b[d] = rho a_d: <b[d] psi'> = D'[d] over the full range
+    T Dp[3][5], b[3][5];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      T R[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) R[v] = D[d * 5 + v] * irho;
-      micro_slope(p, K, ik3, R, a[d]);
+      to_frame(D + 5 * d, V, W, kv, Dp[d]);
+      sv.solve(Dp[d], b[d]);
     }
-    // W0 and its slopes (half-space split)
-    T t[5];
-    mvec<0, 0, 0>(mh, t);
+    // Euler time derivative of the side: rho E = <(a.u) psi> over the full range, with the lab
+    // tangential velocities v = v' + V, w = w' + W (and <b[d] psi'> = D'[d]); A from compatibility
+    T E[5], B[5];
+    tslope<1, true>(mf, b[0], E);
+    tslope_t<0, 2>(mf, b[1], E);
+    tslope_t<0, 3>(mf, b[2], E);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      W0[v] += p.rho * t[v];
-      SP[3][v] += p.rho * t[v];
+    for (int v = 0; v < 5; ++v) E[v] = E[v] + V * Dp[1][v] + W * Dp[2][v];
+    {
+      T RA[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) RA[v] = -E[v];
+      sv.solve(RA, B);
     }
+    // the side's pieces on its half space
+    T w0[5], dw[3][5], s0[5], s1[5], s2[5], s4[5], s5[5];
+    tpsi<0>(mh, p.rho, w0);
+    tpsi<1>(mh, p.rho, s0);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) smom_acc<0, 0, 0>(mh, a[d], p.rho, dW0[d]);
-    // Euler time derivative of the side: -rho <(a.u) psi> over the full space; A from compatibility
-    T E[5] = {0, 0, 0, 0, 0};
-    smom_acc<1, 0, 0>(mf, a[0], T(1), E);
-    smom_acc<0, 1, 0>(mf, a[1], T(1), E);
-    smom_acc<0, 0, 1>(mf, a[2], T(1), E);
-    T RA[5], A[5];
+    for (int d = 0; d < 3; ++d) tslope<0, true>(mh, b[d], dw[d]);
+    {
+      T Vb[5], Wb[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      RA[v] = -E[v];
-      eul[s][v] = -p.rho * E[v];
+      for (int v = 0; v < 5; ++v) {
+        Vb[v] = V * b[1][v];
+        Wb[v] = W * b[2][v];
+      }
+      tslope<2, true>(mh, b[0], s1);
+      tslope_t<1, 2>(mh, b[1], s1);
+      tslope<1>(mh, Vb, s1);
+      tslope_t<1, 3>(mh, b[2], s1);
+      tslope<1>(mh, Wb, s1);
     }
-    micro_slope(p, K, ik3, RA, A);
-    // the side's pieces of f on its half space
-    mvec<1, 0, 0>(mh, t);
+    tslope<1, true>(mh, B, s2);
+    tslope<1, true>(mh, b[0], s4);
+    tslope_t<0, 2>(mh, b[1], s4);
+    tslope_t<0, 3>(mh, b[2], s4);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) SP[0][v] += p.rho * t[v];
-    smom_acc<2, 0, 0>(mh, a[0], p.rho, SP[1]);
-    smom_acc<1, 1, 0>(mh, a[1], p.rho, SP[1]);
-    smom_acc<1, 0, 1>(mh, a[2], p.rho, SP[1]);
-    smom_acc<1, 0, 0>(mh, A, p.rho, SP[2]);
-    // interface moments (needed for Q^n, which also enters the heat-flux correction)
-    smom_acc<1, 0, 0>(mh, a[0], p.rho, SP[4]);
-    smom_acc<0, 1, 0>(mh, a[1], p.rho, SP[4]);
-    smom_acc<0, 0, 1>(mh, a[2], p.rho, SP[4]);
-    smom_acc<0, 0, 0>(mh, A, p.rho, SP[5]);
+    for (int v = 0; v < 5; ++v) s4[v] = s4[v] + V * dw[1][v] + W * dw[2][v];
+    tslope<0, true>(mh, B, s5);
+    if (s == 0) {
+      from_frame<true, true>(w0, V, W, kv, W0);
+      from_frame<true, true>(s0, V, W, kv, SP[0]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) from_frame<true>(dw[d], V, W, kv, dW0[d]);
+      from_frame<true>(s1, V, W, kv, SP[1]);
+      from_frame<true>(s2, V, W, kv, SP[2]);
+      from_frame<true>(s4, V, W, kv, SP[4]);
+      from_frame<true>(s5, V, W, kv, SP[5]);
+    } else {
+      from_frame<false, true>(w0, V, W, kv, W0);
+      from_frame<false, true>(s0, V, W, kv, SP[0]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) from_frame<false>(dw[d], V, W, kv, dW0[d]);
+      from_frame<false>(s1, V, W, kv, SP[1]);
+      from_frame<false>(s2, V, W, kv, SP[2]);
+      from_frame<false>(s4, V, W, kv, SP[4]);
+      from_frame<false>(s5, V, W, kv, SP[5]);
+    }
+    if constexpr (NOUT > 10) {
+      from_frame<true>(E, V, W, kv, eul[s]);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) eul[s][v] = -eul[s][v];
+    }
   }
 
-  // interface equilibrium g0
+  // interface equilibrium g0, in its own tangential frame
   Prim<T> p0;
   p0.rho = W0[0];
   const T ir0 = drcp(W0[0]);
@@ -278,47 +363,53 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
   const T pe = T(gm1) * (W0[4] - T(0.5) * W0[0] * (p0.U * p0.U + p0.V * p0.V + p0.W * p0.W));
   p0.var = pe * ir0;
   p0.lam = T(0.5) * drcp(p0.var);
-  Mom<T> m0;
-  maxwell_moments<0>(p0, K, m0);
-  T ab[3][5];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    T R[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) R[v] = dW0[d][v] * ir0;
-    micro_slope(p0, K, ik3, R, ab[d]);
-  }
-  T G[6][5];  // rho0 x {<u psi>, <u (ab.u) psi>, <u Ab psi>, <psi>, <(ab.u) psi>, <Ab psi>}
-#pragma unroll
-  for (int i = 0; i < 6; ++i)
-#pragma unroll
-    for (int v = 0; v < 5; ++v) G[i][v] = T(0);
-  T Ab[5];
+  // G = rho0 x {<u psi>, <u (ab.u) psi>, <u Ab psi>, -, <(ab.u) psi>}; <Ab psi> = -<(ab.u) psi>
+  T G[5][5];
   {
-    T E[5] = {0, 0, 0, 0, 0};
-    smom_acc<1, 0, 0>(m0, ab[0], T(1), E);
-    smom_acc<0, 1, 0>(m0, ab[1], T(1), E);
-    smom_acc<0, 0, 1>(m0, ab[2], T(1), E);
-    T RA[5];
+    const T V = p0.V, W = p0.W, kv = T(0.5) * (V * V + W * W);
+    FrameMom<T> m0;
+    frame_moments<0>(p0, K, m0);
+    SlopeSolver<T> sv;
+    sv.init(p0, K, ik3);
+    T Dp[3][5], bb[3][5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      RA[v] = -E[v];
-      G[4][v] = p0.rho * E[v];
-      G[3][v] = W0[v];
+    for (int d = 0; d < 3; ++d) {
+      to_frame(dW0[d], V, W, kv, Dp[d]);
+      sv.solve(Dp[d], bb[d]);
     }
-    micro_slope(p0, K, ik3, RA, Ab);
-  }
-  {
-    T t[5];
-    mvec<1, 0, 0>(m0, t);
+    T E[5], Bb[5];
+    tslope<1, true>(m0, bb[0], E);
+    tslope_t<0, 2>(m0, bb[1], E);
+    tslope_t<0, 3>(m0, bb[2], E);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) G[0][v] = p0.rho * t[v];
+    for (int v = 0; v < 5; ++v) E[v] = E[v] + V * Dp[1][v] + W * Dp[2][v];
+    {
+      T RA[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) RA[v] = -E[v];
+      sv.solve(RA, Bb);
+    }
+    T g0[5], g1[5], g2[5];
+    tpsi<1>(m0, p0.rho, g0);
+    {
+      T Vb[5], Wb[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        Vb[v] = V * bb[1][v];
+        Wb[v] = W * bb[2][v];
+      }
+      tslope<2, true>(m0, bb[0], g1);
+      tslope_t<1, 2>(m0, bb[1], g1);
+      tslope<1>(m0, Vb, g1);
+      tslope_t<1, 3>(m0, bb[2], g1);
+      tslope<1>(m0, Wb, g1);
+    }
+    tslope<1, true>(m0, Bb, g2);
+    from_frame<true, true>(g0, V, W, kv, G[0]);
+    from_frame<true>(g1, V, W, kv, G[1]);
+    from_frame<true>(g2, V, W, kv, G[2]);
+    from_frame<true>(E, V, W, kv, G[4]);
   }
-  smom_acc<2, 0, 0>(m0, ab[0], p0.rho, G[1]);
-  smom_acc<1, 1, 0>(m0, ab[1], p0.rho, G[1]);
-  smom_acc<1, 0, 1>(m0, ab[2], p0.rho, G[1]);
-  smom_acc<1, 0, 0>(m0, Ab, p0.rho, G[2]);
-  smom_acc<0, 0, 0>(m0, Ab, p0.rho, G[5]);
 
   // collision time (Sec. 4 opening)
   // relative pressure jump |p_l - p_r| / (p_l + p_r): the difference in FP64, the ratio in T
@@ -330,7 +421,8 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
   else
     tau = (T(P.tau_eps) + T(P.tau_c) * jump) * Dt;
 
-  // closed-form coefficients of f^n and f_t^n (time integrals over [0,dt/2] and [0,dt] combined)
+  // closed-form coefficients of f^n and f_t^n (time integrals over [0,dt/2] and [0,dt] combined);
+  // the g0 and side weights of <psi> sum to 1 in f^n and to 0 in f_t^n (cn[0] + cn[3], ct[0] + ct[3])
   const T iDt = T(1.0 / dt);
   const T om = -dexpm1(T(-0.5) * Dt * drcp(tau));  // 1 - e^{-dt/(2 tau)}; tau = 0 gives 1
   const T e1 = T(1) - om;
@@ -347,7 +439,6 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
   ct[0] = T(4) * rom * om * iDt;
   ct[1] = T(4) * rom * (e1 - T(2) * rom);
   ct[2] = T(1) - T(4) * rom * rom;
-  ct[3] = -ct[0];
   ct[4] = -ct[1];
   ct[5] = T(4) * rom * rom;
 
@@ -356,14 +447,14 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
   for (int v = 0; v < 5; ++v) {
     Fn[v] = cn[0] * G[0][v] + cn[1] * G[1][v] + cn[2] * G[2][v] + cn[3] * SP[0][v] +
             cn[4] * SP[1][v] + cn[5] * SP[2][v];
-    Ft[v] = ct[0] * G[0][v] + ct[1] * G[1][v] + ct[2] * G[2][v] + ct[3] * SP[0][v] +
-            ct[4] * SP[1][v] + ct[5] * SP[2][v];
+    Ft[v] = ct[0] * (G[0][v] - SP[0][v]) + ct[1] * G[1][v] + ct[2] * G[2][v] + ct[4] * SP[1][v] +
+            ct[5] * SP[2][v];
   }
+  // Q: g0 contributes W0 (<psi>) and (cn1 - cn2) <(ab.u) psi>; the sides their own pieces
+  const T cq = cn[1] - cn[2];
   T Qn[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v)
-    Qn[v] = cn[0] * G[3][v] + cn[1] * G[4][v] + cn[2] * G[5][v] + cn[3] * SP[3][v] +
-            cn[4] * SP[4][v] + cn[5] * SP[5][v];
+  for (int v = 0; v < 5; ++v) Qn[v] = W0[v] + cq * G[4][v] + cn[4] * SP[4][v] + cn[5] * SP[5][v];
   if (P.mu0 > 0.0 && P.prandtl > 0.0 && P.prandtl != 1.0) {
     const T k2 = T(0.5) * (p0.U * p0.U + p0.V * p0.V + p0.W * p0.W);
     const T qf = Fn[4] - (p0.U * Fn[1] + p0.V * Fn[2] + p0.W * Fn[3]) + k2 * Fn[0];
@@ -376,11 +467,10 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
     out[5 + v] = Ft[v];
   }
   if constexpr (NOUT > 10) {
+    const T ctq = ct[1] - ct[2];
     T Qt[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v)
-      Qt[v] = ct[0] * G[3][v] + ct[1] * G[4][v] + ct[2] * G[5][v] + ct[3] * SP[3][v] +
-              ct[4] * SP[4][v] + ct[5] * SP[5][v];
+    for (int v = 0; v < 5; ++v) Qt[v] = ctq * G[4][v] + ct[4] * SP[4][v] + ct[5] * SP[5][v];
     // w = e^{-dt/tau0}, tau0 = C jump dt; a zero jump gives w = 0
     const T w = dexp(-drcp(T(P.tau_c) * jump));
     const T w1 = T(1) - w;

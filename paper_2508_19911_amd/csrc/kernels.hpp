@@ -75,19 +75,41 @@ struct CoefBlock {
 // differences and the cell's own normalised gradient are kept for GENO.  qa reads the variable's
 // average plane and ga[3] its three gradient planes; oq[s], og[s] are the byte offsets of stencil
 // cell s in a plane of double and of T.
-template <class T, int S = 0, class QA, class GA>
-__host__ __device__ __forceinline__ void gather_coefficients(const Grid& g, const QA& qa, const GA* ga,
-                                                             const uint32_t* oq, const uint32_t* og,
-                                                             double q0, T* a, T* dface, T* g0) {
+//
+// The stencil cells are taken one at a time in a software pipeline: the loads of cell S + GATHER_AHEAD
+// are issued before cell S is accumulated, so a lane keeps GATHER_AHEAD cells of loads in flight
+// instead of waiting for each cell's loads in turn (a full hoist of all 19 cells' loads would not fit
+// the register budget).
+constexpr int GATHER_AHEAD = 2;
+
+template <int S, class T, class QA, class GA>
+__host__ __device__ __forceinline__ void gather_load(const QA& qa, const GA* ga, const uint32_t* oq,
+                                                     const uint32_t* og, double* q, T (*gv)[3]) {
   if constexpr (S < tab::NSTEN) {
+    if constexpr (S != tab::CENTRE) q[S] = qa(oq[S]);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) gv[S][e] = ga[e](og[S]);
+  }
+}
+
+template <class T, int S, class QA, class GA>
+__host__ __device__ __forceinline__ void gather_step(const Grid& g, const QA& qa, const GA* ga,
+                                                     const uint32_t* oq, const uint32_t* og, double q0,
+                                                     double* q, T (*gv)[3], T* a, T* dface, T* g0) {
+  if constexpr (S < tab::NSTEN) {
+    gather_load<S + GATHER_AHEAD, T>(qa, ga, oq, og, q, gv);
+#ifdef __HIP_DEVICE_COMPILE__
+    // the scheduler keeps this order: loads of cell S + GATHER_AHEAD, then the columns of cell S
+    __builtin_amdgcn_sched_barrier(0);
+#endif
     if constexpr (S != tab::CENTRE) {
-      const T x = data<T>(qa(oq[S]) - q0);
+      const T x = data<T>(q[S] - q0);
       op_col<tab::NEIGH_SLOT[S]>(x, a);
 #pragma unroll
       for (int f = 0; f < 6; ++f)
         if (face_slot(f) == tab::NEIGH_SLOT[S]) dface[f] = x;
     }
-    const T gx = T(g.h[0]) * ga[0](og[S]), gy = T(g.h[1]) * ga[1](og[S]), gz = T(g.h[2]) * ga[2](og[S]);
+    const T gx = T(g.h[0]) * gv[S][0], gy = T(g.h[1]) * gv[S][1], gz = T(g.h[2]) * gv[S][2];
     op_col<18 + 3 * S + 0>(gx, a);
     op_col<18 + 3 * S + 1>(gy, a);
     op_col<18 + 3 * S + 2>(gz, a);
@@ -97,11 +119,29 @@ __host__ __device__ __forceinline__ void gather_coefficients(const Grid& g, cons
       g0[2] = gz;
     }
 #ifdef __HIP_DEVICE_COMPILE__
-    // one stencil cell at a time: the scheduler may not hoist its loads above the previous cell
     __builtin_amdgcn_sched_barrier(0);
 #endif
-    gather_coefficients<T, S + 1>(g, qa, ga, oq, og, q0, a, dface, g0);
+    gather_step<T, S + 1>(g, qa, ga, oq, og, q0, q, gv, a, dface, g0);
   }
+}
+
+template <class T, int P = 0, class QA, class GA>
+__host__ __device__ __forceinline__ void gather_prologue(const QA& qa, const GA* ga, const uint32_t* oq,
+                                                         const uint32_t* og, double* q, T (*gv)[3]) {
+  if constexpr (P < GATHER_AHEAD) {
+    gather_load<P, T>(qa, ga, oq, og, q, gv);
+    gather_prologue<T, P + 1>(qa, ga, oq, og, q, gv);
+  }
+}
+
+template <class T, class QA, class GA>
+__host__ __device__ __forceinline__ void gather_coefficients(const Grid& g, const QA& qa, const GA* ga,
+                                                             const uint32_t* oq, const uint32_t* og,
+                                                             double q0, T* a, T* dface, T* g0) {
+  double q[tab::NSTEN];
+  T gv[tab::NSTEN][3];
+  gather_prologue<T>(qa, ga, oq, og, q, gv);
+  gather_step<T, 0>(g, qa, ga, oq, og, q0, q, gv, a, dface, g0);
 }
 
 template <class T, int MODE>  // MODE 0 linear, 1 GENO everywhere, 2 GENO where flagged

@@ -15,6 +15,10 @@ reports for each run:
 
 It also reports the cost ratio GKS-2nd / CGKS-5th. With --fp32, CGKS-5th is also run in the
 FP32-bulk form (GENO, or the trained indicator when present) for context.
+
+With --reference N, CGKS-5th FP64 on N^3 (256^3 for the supersonic flow in the paper) is run as well.
+Each run's E_k(t), eps_S(t) and eps_D(t) histories are compared with it (max relative difference
+over t, and the peak values).
 """
 from __future__ import annotations
 
@@ -54,13 +58,14 @@ def run(cgks, case, precision, t_end, dt_out, label, indicator=None):
             print(f"  {label}: t={t:.2f} steps={steps} Ek={d['Ek']:.5f} ({gpu_s:.0f} s)", flush=True)
     s.close()
     h = np.array(hist)
+    keep_hist = h.round(8).tolist()
     dek = -np.gradient(h[:, 1], h[:, 0])
     stages = 2 if case.scheme == cgks.SCHEME_CGKS5 else 1
     return {"cells": case.N, "grid": case.nx, "steps": steps, "seconds": gpu_s,
             "mcell_stage_per_s": case.N * stages * steps / gpu_s / 1e6,
             "Ek_end": float(h[-1, 1]), "dEk_peak": float(dek.max()), "t_dEk_peak": float(h[int(np.argmax(dek)), 0]),
             "epsS_peak": float(h[:, 2].max()), "t_epsS_peak": float(h[int(np.argmax(h[:, 2])), 0]),
-            "epsD_peak": float(h[:, 3].max())}
+            "epsD_peak": float(h[:, 3].max()), "history": keep_hist}
 
 
 def main():
@@ -69,6 +74,7 @@ def main():
     ap.add_argument("--t-end", type=float, default=10.0)
     ap.add_argument("--dt-out", type=float, default=0.05)
     ap.add_argument("--fp32", action="store_true")
+    ap.add_argument("--reference", type=int, default=0, help="grid of a CGKS-5th FP64 reference run")
     ap.add_argument("--out", default="efficiency.json")
     args = ap.parse_args()
 
@@ -85,7 +91,7 @@ def main():
         paper = {"cgks5_seconds": 407, "gks2_seconds": 2842, "ratio": 7.0, "hardware": "4x RTX 4090, FP64"}
     out = {"flow": args.flow, "t_end": args.t_end, "cfl": c5.cfl, "paper_table": paper, "runs": {}}
     out["runs"]["cgks5_fp64"] = run(cgks, c5, cgks.PREC_FP64, args.t_end, args.dt_out, "cgks5_fp64")
-    print(json.dumps(out["runs"]["cgks5_fp64"]), flush=True)
+    print(json.dumps({k: v for k, v in out["runs"]["cgks5_fp64"].items() if k != "history"}), flush=True)
     if args.fp32:
         ind = None
         path = os.path.join(HERE, "indicator.npz")
@@ -94,10 +100,25 @@ def main():
             ind = (z["params"].astype(np.float32), float(z["logit_threshold"]))
         c5f = c5.with_(recon=cgks.RECON_LEARNED) if ind is not None else c5
         out["runs"]["cgks5_fp32"] = run(cgks, c5f, cgks.PREC_FP32_BULK, args.t_end, args.dt_out, "cgks5_fp32", ind)
-        print(json.dumps(out["runs"]["cgks5_fp32"]), flush=True)
+        print(json.dumps({k: v for k, v in out["runs"]["cgks5_fp32"].items() if k != "history"}), flush=True)
     out["runs"]["gks2_fp64"] = run(cgks, c2, cgks.PREC_FP64, args.t_end, args.dt_out, "gks2_fp64")
-    print(json.dumps(out["runs"]["gks2_fp64"]), flush=True)
+    print(json.dumps({k: v for k, v in out["runs"]["gks2_fp64"].items() if k != "history"}), flush=True)
     out["cost_ratio_gks2_over_cgks5"] = out["runs"]["gks2_fp64"]["seconds"] / out["runs"]["cgks5_fp64"]["seconds"]
+    if args.reference:
+        cref = c5.with_(nx=args.reference, ny=args.reference, nz=args.reference, recon=cgks.RECON_NONLINEAR)
+        ref = run(cgks, cref, cgks.PREC_FP64, args.t_end, args.dt_out, f"cgks5_fp64_{args.reference}")
+        out["runs"]["reference"] = ref
+        hr = np.array(ref["history"])
+        cmp = {}
+        for name, r in out["runs"].items():
+            if name == "reference":
+                continue
+            h = np.array(r["history"])
+            m = min(len(h), len(hr))
+            cmp[name] = {f"max_rel_diff_{q}": float(np.abs(h[:m, c] - hr[:m, c]).max() / np.abs(hr[:m, c]).max())
+                         for q, c in (("Ek", 1), ("epsS", 2), ("epsD", 3))}
+        out["against_reference"] = cmp
+        print(json.dumps(cmp, indent=1), flush=True)
     print(f"cost ratio GKS-2nd / CGKS-5th = {out['cost_ratio_gks2_over_cgks5']:.2f} (paper: {paper['ratio']})",
           flush=True)
     with open(args.out, "w") as fh:

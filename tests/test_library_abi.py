@@ -88,7 +88,7 @@ def test_flop_counts_are_current():
     fresh = build.count_flops(verbose=False)
     assert fresh == stored
     # the face flux dominates a stage: three launches per stage
-    assert 3 * fresh["flux_launch_per_cell"] > 0.8 * fresh["cell_stage_geno"]
+    assert 3 * fresh["flux_launch_per_cell"] > 0.7 * fresh["cell_stage_geno"]
 
 
 def test_grid_limit_rejected_before_any_device_work():
