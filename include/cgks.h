@@ -121,6 +121,13 @@ int cgks_stage_sampled(void* ctx, double dt, const long* cells, long n, double* 
                        double* sqn, double* sqt);
 
 int cgks_diagnostics(void* ctx, double rho0, double u0, cgks_diag* out);
+/* The same diagnostics with Ek, epsS, epsD, epsT integrated by 3x3x3 Gauss-Legendre quadrature over
+ * each cell's reconstruction of the current state (Sec. 4.1, 4.2: values and velocity derivatives at
+ * the quadrature points come from the reconstruction): CGKS-5th its P^4 polynomial with the GENO
+ * blend (LINEAR: none; NONLINEAR and LEARNED: every cell), GKS-2nd its (limited) P^1.  mu follows
+ * the temperature at each point.  The other fields are those of cgks_diagnostics.  Overwrites the
+ * workspace's coefficient (slope) planes; the state is unchanged.  Synchronous. */
+int cgks_diagnostics_quad(void* ctx, double rho0, double u0, cgks_diag* out);
 /* Flags (1 byte per cell): the cells on which the nonlinear blend ran in the last stage (GENO, or
  * the limiter of GKS2): 0 everywhere for LINEAR, 1 for NONLINEAR, the network's decision for LEARNED. */
 int cgks_get_flags(void* ctx, unsigned char* flags);

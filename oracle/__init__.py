@@ -55,6 +55,7 @@ def lib():
         L.cgkso_step.argtypes = [P, I, D, D, ctypes.POINTER(I), dp]
         L.cgkso_step_fixed.argtypes = [P, I, D]
         L.cgkso_diagnostics.argtypes = [P, D, D, P]
+        L.cgkso_diagnostics_quad.argtypes = [P, D, D, P]
         L.cgkso_get_flags.argtypes = [P, P]
         L.cgkso_moments.argtypes = [P, D, I, I, P, P, P, P]
         L.cgkso_micro_slope.argtypes = [P, D, P, P]
@@ -160,9 +161,12 @@ class Oracle:
     def step_fixed(self, nsteps, dt):
         return lib().cgkso_step_fixed(self.h, int(nsteps), float(dt))
 
-    def diagnostics(self, rho0=1.0, u0=1.0):
+    def diagnostics(self, rho0=1.0, u0=1.0, quad=False):
+        """One-point diagnostics, or (quad=True) Ek and the dissipation rates by 3x3x3 Gauss quadrature
+        of the reconstruction."""
         out = np.zeros(16)
-        lib().cgkso_diagnostics(self.h, float(rho0), float(u0), _ptr(out))
+        (lib().cgkso_diagnostics_quad if quad else lib().cgkso_diagnostics)(self.h, float(rho0), float(u0),
+                                                                           _ptr(out))
         keys = ["Ek", "epsS", "epsD", "epsT", "mass", "momx", "momy", "momz", "energy", "rho_min",
                 "p_min", "flagged_fraction", "t", "step"]
         return dict(zip(keys, out[:14].tolist()))

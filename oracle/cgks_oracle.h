@@ -67,6 +67,10 @@ int  cgkso_step_fixed(void* ctx, int nsteps, double dt);
 /* out[16]: Ek, epsS, epsD, epsT, mass, momx, momy, momz, energy, rho_min, p_min,
  * flagged_fraction, t, step, 0, 0.  rho0, u0 normalise Ek and the dissipation rates. */
 int  cgkso_diagnostics(void* ctx, double rho0, double u0, double* out);
+/* The same with Ek, epsS, epsD, epsT integrated over each cell by the 3-point Gauss-Legendre rule per
+ * axis applied to the cell's reconstruction (values and velocity derivatives at the points from it;
+ * CGKS-5th P^4 with GENO for NONLINEAR and LEARNED, GKS-2nd its P^1, limited for NONLINEAR). */
+int  cgkso_diagnostics_quad(void* ctx, double rho0, double u0, double* out);
 /* Per-cell GENO flag used by the last stage (LEARNED) -- 1 byte per cell. */
 int  cgkso_get_flags(void* ctx, unsigned char* flags);
 

@@ -24,12 +24,17 @@ void face_gauss_points(double gp[4][2]);
 // scale: the variable's magnitude squared, for the smoothness floor of the GENO path function
 void recon_cell(const cgkso_params& P, const double* q, const double (*g)[3], const double h[3],
                 double scale, int mode, double out[6][4][4], double info[4]);
+// the same reconstruction evaluated at npts normalised points x: out[n] = (value, d/dx, d/dy, d/dz)
+void recon_cell_at(const cgkso_params& P, const double* q, const double (*g)[3], const double h[3],
+                   double scale, int mode, int npts, const double (*x)[3], double (*out)[4]);
 // the GENO scale of variable v of the conservative state q[5]: rho^2, 2 rho rhoE, (rhoE)^2
 double geno_scale(const double* q5, int v);
 // GKS-2nd: one variable of one cell from q[7] (cell, -x,+x,-y,+y,-z,+z): face-centre values
 // and slopes, out[6][4].
 void recon_cell_gks2(const cgkso_params& P, const double* q7, const double h[3], int limited,
                      double out[6][4]);
+void recon_cell_gks2_at(const cgkso_params& P, const double* q7, const double h[3], int limited, int npts,
+                        const double (*x)[3], double (*out)[4]);
 
 /* MLP (mlp.cpp) */
 void mlp_forward(const float* params, const float* x, long n, int bf16, double* logits);

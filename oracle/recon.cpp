@@ -203,14 +203,16 @@ static const double* is_gram() {
   return G.data();
 }
 
-void recon_cell(const cgkso_params& P, const double* q, const double (*g)[3], const double h[3],
-                double scale, int mode, double out[6][4][4], double info[4]) {
+// The reconstruction of one cell as a polynomial: a (coefficients of P^4 on the zero-mean basis), and
+// for GENO the blend weight chi and the combined linear slope bbar (chi = 1, bbar = 0 otherwise).
+static void recon_poly(const cgkso_params& P, const double* q, const double (*g)[3], const double h[3],
+                       double scale, int mode, double a[NB], double* chi_out, double bbar[3],
+                       double info[4]) {
   const double* R = recon_operator();
   double data[NCOL];
   for (int n = 0; n < 18; ++n) data[n] = q[n + 1] - q[0];
   for (int c = 0; c < NSTEN; ++c)
     for (int e = 0; e < 3; ++e) data[18 + 3 * c + e] = h[e] * g[c][e];
-  double a[NB];
   for (int i = 0; i < NB; ++i) {
     double s = 0.0;
     for (int c = 0; c < NCOL; ++c) s += R[i * NCOL + c] * data[c];
@@ -218,7 +220,7 @@ void recon_cell(const cgkso_params& P, const double* q, const double (*g)[3], co
   }
 
   double chi = 1.0, ISH = 0.0, ISL = 0.0;
-  double bbar[3] = {0.0, 0.0, 0.0};
+  bbar[0] = bbar[1] = bbar[2] = 0.0;
   if (mode == 1) {
     const double eps = P.geno_eps;
     // six linear sub-stencil polynomials (R3)
@@ -257,20 +259,40 @@ void recon_cell(const cgkso_params& P, const double* q, const double (*g)[3], co
     info[3] = 0.0;
   }
 
+  *chi_out = chi;
+}
+
+// value and physical derivatives of the reconstruction at the normalised point x:
+// eq. (weno-new), Q = chi P^4 + (1-chi) sum_m omega_m P^1_m, the same for the derivatives
+static void eval_poly(const double* q, const double h[3], const double a[NB], double chi,
+                      const double bbar[3], const double x[3], double out[4]) {
+  double val = 0.0, der[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < NB; ++i) {
+    val += a[i] * p_at(i, x);
+    for (int e = 0; e < 3; ++e) der[e] += a[i] * dp_at(i, e, x);
+  }
+  const double lin = bbar[0] * x[0] + bbar[1] * x[1] + bbar[2] * x[2];
+  out[0] = q[0] + chi * val + (1.0 - chi) * lin;
+  for (int e = 0; e < 3; ++e) out[1 + e] = (chi * der[e] + (1.0 - chi) * bbar[e]) / h[e];
+}
+
+void recon_cell(const cgkso_params& P, const double* q, const double (*g)[3], const double h[3],
+                double scale, int mode, double out[6][4][4], double info[4]) {
+  double a[NB], chi, bbar[3];
+  recon_poly(P, q, g, h, scale, mode, a, &chi, bbar, info);
   for (int f = 0; f < 6; ++f)
     for (int k = 0; k < 4; ++k) {
       double x[3];
       face_point(f, k, x);
-      double val = 0.0, der[3] = {0.0, 0.0, 0.0};
-      for (int i = 0; i < NB; ++i) {
-        val += a[i] * p_at(i, x);
-        for (int e = 0; e < 3; ++e) der[e] += a[i] * dp_at(i, e, x);
-      }
-      // eq. (weno-new): Q = chi P^4 + (1-chi) sum_m omega_m P^1_m, same for the derivatives
-      const double lin = bbar[0] * x[0] + bbar[1] * x[1] + bbar[2] * x[2];
-      out[f][k][0] = q[0] + chi * val + (1.0 - chi) * lin;
-      for (int e = 0; e < 3; ++e) out[f][k][1 + e] = (chi * der[e] + (1.0 - chi) * bbar[e]) / h[e];
+      eval_poly(q, h, a, chi, bbar, x, out[f][k]);
     }
+}
+
+void recon_cell_at(const cgkso_params& P, const double* q, const double (*g)[3], const double h[3],
+                   double scale, int mode, int npts, const double (*x)[3], double (*out)[4]) {
+  double a[NB], chi, bbar[3];
+  recon_poly(P, q, g, h, scale, mode, a, &chi, bbar, nullptr);
+  for (int n = 0; n < npts; ++n) eval_poly(q, h, a, chi, bbar, x[n], out[n]);
 }
 
 double geno_scale(const double* q5, int v) {
@@ -279,9 +301,9 @@ double geno_scale(const double* q5, int v) {
   return 2.0 * q5[0] * q5[4];
 }
 
-void recon_cell_gks2(const cgkso_params& P, const double* q7, const double h[3], int limited,
-                     double out[6][4]) {
-  double b[3];
+// GKS-2nd P^1: central slopes b (per unit of the normalised coordinate) and the limiter factor phi
+static void gks2_slopes(const cgkso_params& P, const double* q7, const double h[3], int limited,
+                        double b[3], double* phi_out) {
   for (int e = 0; e < 3; ++e) b[e] = 0.5 * (q7[2 + 2 * e] - q7[1 + 2 * e]);
   double phi = 1.0;
   if (limited) {
@@ -303,10 +325,27 @@ void recon_cell_gks2(const cgkso_params& P, const double* q7, const double h[3],
       phi = std::fmin(phi, pf);
     }
   }
+  *phi_out = phi;
+}
+
+void recon_cell_gks2(const cgkso_params& P, const double* q7, const double h[3], int limited,
+                     double out[6][4]) {
+  double b[3], phi;
+  gks2_slopes(P, q7, h, limited, b, &phi);
   for (int f = 0; f < 6; ++f) {
     const double s = (f % 2) ? 0.5 : -0.5;
     out[f][0] = q7[0] + phi * s * b[f / 2];
     for (int e = 0; e < 3; ++e) out[f][1 + e] = phi * b[e] / h[e];
+  }
+}
+
+void recon_cell_gks2_at(const cgkso_params& P, const double* q7, const double h[3], int limited, int npts,
+                        const double (*x)[3], double (*out)[4]) {
+  double b[3], phi;
+  gks2_slopes(P, q7, h, limited, b, &phi);
+  for (int n = 0; n < npts; ++n) {
+    out[n][0] = q7[0] + phi * (b[0] * x[n][0] + b[1] * x[n][1] + b[2] * x[n][2]);
+    for (int e = 0; e < 3; ++e) out[n][1 + e] = phi * b[e] / h[e];
   }
 }
 

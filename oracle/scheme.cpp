@@ -573,6 +573,98 @@ int cgkso_diagnostics(void* ctx, double rho0, double u0, double* out) {
   return CGKSO_OK;
 }
 
+// Quadrature form of the diagnostics (Sec. 4.1, 4.2: E_k and the dissipation rates by numerical
+// quadrature, velocity derivatives at the quadrature points from the reconstruction).  The rule is the
+// tensor 3-point Gauss-Legendre rule on the unit cell (reading: the paper does not name its rule).
+int cgkso_diagnostics_quad(void* ctx, double rho0, double u0, double* out) {
+  int rc = cgkso_diagnostics(ctx, rho0, u0, out);
+  if (rc != CGKSO_OK) return rc;
+  Ctx* c = static_cast<Ctx*>(ctx);
+  const cgkso_params& P = c->P;
+  const long N = c->N;
+  const double* Q = c->Q.data();
+  const double* G = c->G.data();
+  const bool c5 = P.scheme == CGKSO_SCHEME_CGKS5;
+  // Gauss-Legendre on [-1/2, 1/2]: 0 and +-sqrt(3/5)/2 with weights 8/18 and 5/18
+  const double xa[3] = {-0.5 * std::sqrt(0.6), 0.0, 0.5 * std::sqrt(0.6)};
+  const double wa[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  double xq[27][3], wq[27];
+  for (int kz = 0; kz < 3; ++kz)
+    for (int ky = 0; ky < 3; ++ky)
+      for (int kx = 0; kx < 3; ++kx) {
+        const int n = (kz * 3 + ky) * 3 + kx;
+        xq[n][0] = xa[kx];
+        xq[n][1] = xa[ky];
+        xq[n][2] = xa[kz];
+        wq[n] = wa[kx] * wa[ky] * wa[kz];
+      }
+  int off[NSTEN][3];
+  stencil_offsets(off);
+  const int mode = P.recon == CGKSO_RECON_LINEAR ? 0 : 1;
+  std::vector<double> cell_sums(3 * N);
+#pragma omp parallel for collapse(2)
+  for (long k = 0; k < P.nz; ++k)
+    for (long j = 0; j < P.ny; ++j)
+      for (long i = 0; i < P.nx; ++i) {
+        const long ci = cell_index(*c, i, j, k);
+        double pt[5][27][4];  // [variable][point][value, d/dx, d/dy, d/dz]
+        if (c5) {
+          double q5[5];
+          for (int v = 0; v < 5; ++v) q5[v] = Q[v * N + ci];
+          for (int v = 0; v < 5; ++v) {
+            double q[NSTEN], g[NSTEN][3];
+            for (int s = 0; s < NSTEN; ++s) {
+              const long sc = cell_index(*c, i + off[s][0], j + off[s][1], k + off[s][2]);
+              q[s] = Q[v * N + sc];
+              for (int e = 0; e < 3; ++e) g[s][e] = G[(5 * e + v) * N + sc];
+            }
+            recon_cell_at(P, q, g, c->h, geno_scale(q5, v), mode, 27, xq, pt[v]);
+          }
+        } else {
+          for (int v = 0; v < 5; ++v) {
+            double q7[7];
+            q7[0] = Q[v * N + ci];
+            for (int d = 0; d < 3; ++d) {
+              q7[1 + 2 * d] = Q[v * N + cell_index(*c, i - (d == 0), j - (d == 1), k - (d == 2))];
+              q7[2 + 2 * d] = Q[v * N + cell_index(*c, i + (d == 0), j + (d == 1), k + (d == 2))];
+            }
+            recon_cell_gks2_at(P, q7, c->h, P.recon == CGKSO_RECON_NONLINEAR ? 1 : 0, 27, xq, pt[v]);
+          }
+        }
+        double ek = 0.0, es = 0.0, ed = 0.0;
+        for (int n = 0; n < 27; ++n) {
+          double q[5], prim[5], p;
+          for (int v = 0; v < 5; ++v) q[v] = pt[v][n][0];
+          cons_to_prim(q, P.gamma, prim, &p);
+          const double rho = prim[0];
+          double du[3][3];  // du[a][d] = d U_a / d x_d = (d m_a/dx_d - U_a d rho/dx_d) / rho
+          for (int d = 0; d < 3; ++d)
+            for (int a = 0; a < 3; ++a) du[a][d] = (pt[1 + a][n][1 + d] - prim[1 + a] * pt[0][n][1 + d]) / rho;
+          const double wx = du[2][1] - du[1][2], wy = du[0][2] - du[2][0], wz = du[1][0] - du[0][1];
+          const double div = du[0][0] + du[1][1] + du[2][2];
+          const double mu = viscosity(P, p / rho);
+          ek += wq[n] * 0.5 * rho * (prim[1] * prim[1] + prim[2] * prim[2] + prim[3] * prim[3]);
+          es += wq[n] * mu * (wx * wx + wy * wy + wz * wz);
+          ed += wq[n] * mu * div * div;
+        }
+        cell_sums[3 * ci + 0] = ek;
+        cell_sums[3 * ci + 1] = es;
+        cell_sums[3 * ci + 2] = ed;
+      }
+  double ek = 0.0, es = 0.0, ed = 0.0;
+  for (long n = 0; n < N; ++n) {
+    ek += cell_sums[3 * n + 0];
+    es += cell_sums[3 * n + 1];
+    ed += cell_sums[3 * n + 2];
+  }
+  const double norm = 1.0 / (rho0 * u0 * u0 * static_cast<double>(N));
+  out[0] = ek * norm;
+  out[1] = es * norm;
+  out[2] = 4.0 / 3.0 * ed * norm;
+  out[3] = out[1] + out[2];
+  return CGKSO_OK;
+}
+
 int cgkso_get_flags(void* ctx, unsigned char* flags) {
   Ctx* c = static_cast<Ctx*>(ctx);
   std::memcpy(flags, c->flags.data(), c->N);

@@ -25,7 +25,7 @@ ERRORS = {0: "ok", -1: "EINVAL", -2: "EWORKSPACE", -3: "EDEVICE", -4: "ENONPHYSI
 SYMBOLS = [
     "cgks_workspace_bytes", "cgks_create", "cgks_destroy", "cgks_set_state", "cgks_set_ic",
     "cgks_get_state", "cgks_compute_dt", "cgks_step", "cgks_step_fixed", "cgks_stage", "cgks_stage_sampled",
-    "cgks_diagnostics", "cgks_get_flags", "cgks_indicator_set", "cgks_indicator_get",
+    "cgks_diagnostics", "cgks_diagnostics_quad", "cgks_get_flags", "cgks_indicator_set", "cgks_indicator_get",
     "cgks_features", "cgks_indicator_logits", "cgks_labels", "cgks_indicator_train",
     "cgks_indicator_grad", "cgks_timing_enable", "cgks_timing_read", "cgks_debug_point_flux",
     "cgks_debug_coefficients", "cgks_strerror",
@@ -87,6 +87,7 @@ def load():
     L.cgks_stage.argtypes = [P, D, P, P, P, P]
     L.cgks_stage_sampled.argtypes = [P, D, P, ctypes.c_long, P, P, P, P]
     L.cgks_diagnostics.argtypes = [P, D, D, ctypes.POINTER(Diag)]
+    L.cgks_diagnostics_quad.argtypes = [P, D, D, ctypes.POINTER(Diag)]
     L.cgks_get_flags.argtypes = [P, P]
     L.cgks_indicator_set.argtypes = [P, P, Z, D]
     L.cgks_indicator_get.argtypes = [P, P, Z]
@@ -204,9 +205,12 @@ class Solver:
             self.h, float(dt), _p(cells), n, _p(L), _p(Lt), _p(sqn) if c5 else None, _p(sqt) if c5 else None))
         return L, Lt, sqn, sqt
 
-    def diagnostics(self, rho0=1.0, u0=1.0):
+    def diagnostics(self, rho0=1.0, u0=1.0, quad=False):
+        """One-point diagnostics of the cell averages, or (quad=True) Ek and the dissipation rates by
+        3x3x3 Gauss quadrature of the reconstruction."""
         d = Diag()
-        _check("cgks_diagnostics", load().cgks_diagnostics(self.h, float(rho0), float(u0), ctypes.byref(d)))
+        name = "cgks_diagnostics_quad" if quad else "cgks_diagnostics"
+        _check(name, getattr(load(), name)(self.h, float(rho0), float(u0), ctypes.byref(d)))
         return {k: getattr(d, k) for k, _ in Diag._fields_[:14]}
 
     def flags(self):

@@ -168,7 +168,7 @@ int run_flags(Ctx& c, const double* Q, const T* G) {
 
 template <class T>
 int launch_coef(Ctx& c, const double* Q, const T* G) {
-  const dim3 grid(c.nblk), blk(BLK);
+  const dim3 grid(c.nblk, 5), blk(BLK);  // y: the conservative variable
   T* C = c.at<T>(c.L.C);
   const unsigned char* fl = c.at<unsigned char>(c.L.flags);
   TimedScope ts(c, CGKS_KC_COEF);
@@ -295,6 +295,38 @@ double dt_from_limits(const Ctx& c, const double lim[3], double cfl) {
 }  // namespace
 
 // ============================================================================ C ABI
+// quadrature form of Ek, epsS, epsD on the reconstruction of the current state (the coefficient /
+// slope planes of the workspace are overwritten; the state is not)
+template <class T>
+int diag_quad(Ctx& c, double* r) {
+  const double* Q = c.at<double>(c.L.Q);
+  T* C = c.at<T>(c.L.C);
+  double* part = c.at<double>(c.L.red);
+  double* scal = c.at<double>(c.L.scal);
+  const dim3 grid(c.nblk), blk(BLK);
+  if (c.p.scheme == CGKS_SCHEME_CGKS5) {
+    const T* G = c.at<T>(c.L.G);
+    const unsigned char* fl = c.at<unsigned char>(c.L.flags);
+    const dim3 cgrid(c.nblk, 5);
+    if (c.p.recon == CGKS_RECON_LINEAR)
+      k_coef<T, 0><<<cgrid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp);
+    else  // GENO everywhere (also for the learned form)
+      k_coef<T, 1><<<cgrid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp);
+    k_diag_quad5<T><<<grid, blk, 0, c.stream>>>(c.g, Q, C, c.fp, part);
+  } else {
+    if (c.p.recon == CGKS_RECON_NONLINEAR)
+      k_slopes2<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, C, c.vk_eps2);
+    else
+      k_slopes2<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, C, c.vk_eps2);
+    k_diag_quad2<T><<<grid, blk, 0, c.stream>>>(c.g, Q, C, c.fp, part);
+  }
+  k_diag_final<<<1, BLK, 0, c.stream>>>(c.nblk, part, scal);
+  LAUNCHCK("k_diag_quad");
+  HIPCK(hipMemcpyAsync(r, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  HIPCK(hipStreamSynchronize(c.stream));
+  return CGKS_OK;
+}
+
 extern "C" {
 
 int cgks_workspace_bytes(const cgks_params* p, size_t* bytes) {
@@ -667,6 +699,22 @@ int cgks_diagnostics(void* ctx, double rho0, double u0, cgks_diag* out) {
   out->t = c.t;
   out->step = (double)c.step;
   out->reserved[0] = out->reserved[1] = 0.0;
+  return CGKS_OK;
+}
+
+int cgks_diagnostics_quad(void* ctx, double rho0, double u0, cgks_diag* out) {
+  if (!ctx) return CGKS_EINVAL;
+  int rc = cgks_diagnostics(ctx, rho0, u0, out);
+  if (rc) return rc;
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  double r[3];
+  rc = c.p.precision == CGKS_PREC_FP64 ? diag_quad<double>(c, r) : diag_quad<float>(c, r);
+  if (rc) return rc;
+  const double norm = 1.0 / (rho0 * u0 * u0 * (double)c.g.N);
+  out->Ek = r[0] * norm;
+  out->epsS = r[1] * norm;
+  out->epsD = 4.0 / 3.0 * r[2] * norm;
+  out->epsT = out->epsS + out->epsD;
   return CGKS_OK;
 }
 

@@ -76,11 +76,15 @@ struct CoefBlock {
 // average plane and ga[3] its three gradient planes; oq[s], og[s] are the byte offsets of stencil
 // cell s in a plane of double and of T.
 //
-// The stencil cells are taken one at a time in a software pipeline: the loads of cell S + GATHER_AHEAD
-// are issued before cell S is accumulated, so a lane keeps GATHER_AHEAD cells of loads in flight
-// instead of waiting for each cell's loads in turn (a full hoist of all 19 cells' loads would not fit
-// the register budget).
-constexpr int GATHER_AHEAD = 2;
+// The stencil cells are taken one at a time in a software pipeline: the loads of the cell
+// GATHER_AHEAD positions later are issued before a cell is accumulated, so a lane keeps
+// GATHER_AHEAD cells of loads in flight (a full hoist of all 19 cells' loads would not fit the
+// register budget).
+#ifndef CGKS_GATHER_AHEAD
+#define CGKS_GATHER_AHEAD 2
+#endif
+constexpr int GATHER_AHEAD = CGKS_GATHER_AHEAD;
+static_assert(GATHER_AHEAD >= 1 && GATHER_AHEAD < tab::NSTEN, "gather pipeline depth");
 
 template <int S, class T, class QA, class GA>
 __host__ __device__ __forceinline__ void gather_load(const QA& qa, const GA* ga, const uint32_t* oq,
@@ -99,7 +103,7 @@ __host__ __device__ __forceinline__ void gather_step(const Grid& g, const QA& qa
   if constexpr (S < tab::NSTEN) {
     gather_load<S + GATHER_AHEAD, T>(qa, ga, oq, og, q, gv);
 #ifdef __HIP_DEVICE_COMPILE__
-    // the scheduler keeps this order: loads of cell S + GATHER_AHEAD, then the columns of cell S
+    // the scheduler keeps this order: the loads GATHER_AHEAD cells ahead, then the columns of cell S
     __builtin_amdgcn_sched_barrier(0);
 #endif
     if constexpr (S != tab::CENTRE) {
@@ -144,12 +148,16 @@ __host__ __device__ __forceinline__ void gather_coefficients(const Grid& g, cons
   gather_step<T, 0>(g, qa, ga, oq, og, q0, q, gv, a, dface, g0);
 }
 
+// One thread per (cell, variable): blockIdx.y is the variable.  A thread's loads all precede its
+// stores, so no load waits behind the completion of earlier coefficient stores (loads and stores
+// share one completion counter, in issue order).
 template <class T, int MODE>  // MODE 0 linear, 1 GENO everywhere, 2 GENO where flagged
 __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__ Q,
                                               const T* __restrict__ G,
                                               const unsigned char* __restrict__ flags,
                                               T* __restrict__ C, GenoParams gp) {
   const int cell = blockIdx.x * BLK + threadIdx.x;
+  const int v = blockIdx.y;
   if (cell >= g.N) return;
   int i, j, k;
   cell_ijk(g, cell, i, j, k);
@@ -165,29 +173,30 @@ __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__
   }
   bool geno = MODE == 1;
   if constexpr (MODE == 2) geno = flags[cell] != 0;
-  double q5[5];
+  const BufPlane<double> qa(Q + v * N, N);
+  const BufPlane<T> ga[3] = {BufPlane<T>(G + v * N, N), BufPlane<T>(G + (5 + v) * N, N),
+                             BufPlane<T>(G + (10 + v) * N, N)};
+  const double q0 = ld(Q + v * N, (uint32_t)cell);
+  T a[tab::NB], dface[6], g0[3];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) q5[v] = ld(Q + v * N, (uint32_t)cell);
-#pragma unroll 1
-  for (int v = 0; v < 5; ++v) {
-    const BufPlane<double> qa(Q + v * N, N);
-    const BufPlane<T> ga[3] = {BufPlane<T>(G + v * N, N), BufPlane<T>(G + (5 + v) * N, N),
-                               BufPlane<T>(G + (10 + v) * N, N)};
-    T a[tab::NB], dface[6], g0[3];
+  for (int m = 0; m < tab::NB; ++m) a[m] = T(0);
+  gather_coefficients<T>(g, qa, ga, oq, og, q0, a, dface, g0);
+  if (MODE != 0 && geno) {
+    // the GENO floor scale of this variable needs rho and rhoE of the cell
+    double q5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    q5[0] = ld(Q, (uint32_t)cell);
+    q5[4] = ld(Q + 4 * N, (uint32_t)cell);
+    geno_blend(dface, g0, a, gp, data<T>(gp.eps + gp.hmax2 * geno_scale(q5, v)));
+  }
+  using CB = CoefBlock<T>;
+  using V = typename Vec16<T>::type;
+  T* cb = C + CB::base(cell, v);
 #pragma unroll
-    for (int m = 0; m < tab::NB; ++m) a[m] = T(0);
-    gather_coefficients<T>(g, qa, ga, oq, og, q5[v], a, dface, g0);
-    if (MODE != 0 && geno) geno_blend(dface, g0, a, gp, data<T>(gp.eps + gp.hmax2 * geno_scale(q5, v)));
-    using CB = CoefBlock<T>;
-    using V = typename Vec16<T>::type;
-    T* cb = C + CB::base(cell, v);
+  for (int c = 0; c < CB::NCH; ++c) {
+    V x;
 #pragma unroll
-    for (int j = 0; j < CB::NCH; ++j) {
-      V x;
-#pragma unroll
-      for (int e = 0; e < CB::PER; ++e) x[e] = j * CB::PER + e < tab::NB ? a[j * CB::PER + e] : T(0);
-      *reinterpret_cast<V*>(cb + j * CB::CHUNK_STRIDE) = x;
-    }
+    for (int e = 0; e < CB::PER; ++e) x[e] = c * CB::PER + e < tab::NB ? a[c * CB::PER + e] : T(0);
+    *reinterpret_cast<V*>(cb + c * CB::CHUNK_STRIDE) = x;
   }
 }
 
@@ -346,38 +355,60 @@ __global__ __launch_bounds__(BLK) void k_update5(Grid g, const T* __restrict__ F
   T* GQn = static_cast<T*>(o.GQn);
   T* Gs = static_cast<T*>(o.Gs);
   T* Gf = static_cast<T*>(o.G);
+  // every load first, then every store: loads and stores complete in issue order on one counter,
+  // so a load issued after a store would wait for the store
+  double L[5], Lt[5], sn[3][5], st[3][5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    double L = 0.0, Lt = 0.0;
+    L[v] = 0.0;
+    Lt[v] = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const T* Fd = F + (long long)(d * 30) * N;
-      L -= (double(Fd[v * N + cp[d]]) - double(Fd[v * N + cell])) * g.ih[d];
-      Lt -= (double(Fd[(5 + v) * N + cp[d]]) - double(Fd[(5 + v) * N + cell])) * g.ih[d];
+      L[v] -= (double(Fd[v * N + cp[d]]) - double(Fd[v * N + cell])) * g.ih[d];
+      Lt[v] -= (double(Fd[(5 + v) * N + cp[d]]) - double(Fd[(5 + v) * N + cell])) * g.ih[d];
       // this cell is the left cell of its + face and the right cell of its - face
-      const double sn = (double(Fd[(10 + v) * N + cp[d]]) - double(Fd[(20 + v) * N + cell])) * g.ih[d];
-      const double st = (double(Fd[(15 + v) * N + cp[d]]) - double(Fd[(25 + v) * N + cell])) * g.ih[d];
+      if constexpr (STAGE != 2)
+        sn[d][v] = (double(Fd[(10 + v) * N + cp[d]]) - double(Fd[(20 + v) * N + cell])) * g.ih[d];
+      st[d][v] = (double(Fd[(15 + v) * N + cp[d]]) - double(Fd[(25 + v) * N + cell])) * g.ih[d];
+    }
+  }
+  double q[5];
+  if constexpr (STAGE == 1) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q[v] = Qn[v * N + cell];
+  } else if constexpr (STAGE == 2) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      q[v] = o.Acc[v * N + cell];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sn[d][v] = double(GQn[(d * 5 + v) * N + cell]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
       const long long gi = (d * 5 + v) * N + cell;
       if constexpr (STAGE == 0) {
-        GQn[gi] = T(sn);
-        Gs[gi] = T(st);
+        GQn[gi] = T(sn[d][v]);
+        Gs[gi] = T(st[d][v]);
       } else if constexpr (STAGE == 1) {
-        GQn[gi] = T(sn);
-        Gs[gi] = T(sn + 0.5 * dt * st);
+        GQn[gi] = T(sn[d][v]);
+        Gs[gi] = T(sn[d][v] + 0.5 * dt * st[d][v]);
       } else {
-        Gf[gi] = T(double(GQn[gi]) + dt * st);
+        Gf[gi] = T(sn[d][v] + dt * st[d][v]);
       }
     }
     const long long qi = v * N + cell;
     if constexpr (STAGE == 0) {
-      o.Acc[qi] = L;
-      o.Qs[qi] = Lt;
+      o.Acc[qi] = L[v];
+      o.Qs[qi] = Lt[v];
     } else if constexpr (STAGE == 1) {
-      const double q = Qn[qi];
-      o.Qs[qi] = q + 0.5 * dt * L + 0.125 * dt * dt * Lt;
-      o.Acc[qi] = q + dt * L + dt * dt / 6.0 * Lt;
+      o.Qs[qi] = q[v] + 0.5 * dt * L[v] + 0.125 * dt * dt * Lt[v];
+      o.Acc[qi] = q[v] + dt * L[v] + dt * dt / 6.0 * Lt[v];
     } else {
-      o.Q[qi] = o.Acc[qi] + dt * dt / 3.0 * Lt;
+      o.Q[qi] = q[v] + dt * dt / 3.0 * Lt[v];
     }
   }
 }
@@ -394,12 +425,18 @@ __global__ __launch_bounds__(BLK) void k_slopes2(Grid g, const double* __restric
   const int nb[6] = {neighbour_m<0>(g, cell, i, j, k), neighbour_p<0>(g, cell, i, j, k),
                      neighbour_m<1>(g, cell, i, j, k), neighbour_p<1>(g, cell, i, j, k),
                      neighbour_m<2>(g, cell, i, j, k), neighbour_p<2>(g, cell, i, j, k)};
+  // all loads before the first store (loads and stores complete in issue order on one counter)
+  double qc[5], qn[5][6];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const double q0 = Q[v * N + cell];
-    double q[6];
+    qc[v] = Q[v * N + cell];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) q[m] = Q[v * N + nb[m]];
+    for (int m = 0; m < 6; ++m) qn[v][m] = Q[v * N + nb[m]];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double q0 = qc[v];
+    const double* q = qn[v];
     double b[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) b[e] = 0.5 * (q[2 * e + 1] - q[2 * e]);
@@ -473,20 +510,27 @@ __global__ __launch_bounds__(BLK) void k_update2(Grid g, const T* __restrict__ F
   const long long N = g.N;
   const int cp[3] = {neighbour_p<0>(g, cell, i, j, k), neighbour_p<1>(g, cell, i, j, k),
                      neighbour_p<2>(g, cell, i, j, k)};
+  // all loads before the first store (loads and stores complete in issue order on one counter)
+  double L[5], Lt[5], q[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    double L = 0.0, Lt = 0.0;
+    L[v] = 0.0;
+    Lt[v] = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const T* Fd = F + (long long)(d * 10) * N;
-      L -= (double(Fd[v * N + cp[d]]) - double(Fd[v * N + cell])) * g.ih[d];
-      Lt -= (double(Fd[(5 + v) * N + cp[d]]) - double(Fd[(5 + v) * N + cell])) * g.ih[d];
+      L[v] -= (double(Fd[v * N + cp[d]]) - double(Fd[v * N + cell])) * g.ih[d];
+      Lt[v] -= (double(Fd[(5 + v) * N + cp[d]]) - double(Fd[(5 + v) * N + cell])) * g.ih[d];
     }
+    if constexpr (!DEBUG) q[v] = Q[v * N + cell];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
     if constexpr (DEBUG) {
-      Lout[v * N + cell] = L;
-      Ltout[v * N + cell] = Lt;
+      Lout[v * N + cell] = L[v];
+      Ltout[v * N + cell] = Lt[v];
     } else {
-      Q[v * N + cell] += dt * L + 0.5 * dt * dt * Lt;
+      Q[v * N + cell] = q[v] + (dt * L[v] + 0.5 * dt * dt * Lt[v]);
     }
   }
 }
@@ -635,6 +679,128 @@ __global__ __launch_bounds__(BLK) void k_diag_final(int nblk, const double* __re
   if (threadIdx.x == 0)
 #pragma unroll
     for (int q = 0; q < 11; ++q) out[q] = val[q];
+}
+
+// ============================================================================ quadrature diagnostics
+// E_k, eps_S and eps_D integrated over each cell with the 3x3x3 Gauss-Legendre rule applied to the
+// cell's reconstruction (Sec. 4.1, 4.2: the derivatives at the quadrature points come from the
+// reconstruction): the P^4 coefficients of CGKS-5th (GENO folded in as in the scheme), or the
+// limited P^1 of GKS-2nd.  At each point: rho, m, rhoE and the gradients of rho and m give
+// (1/2) rho |U|^2, mu |curl U|^2 and mu (div U)^2, mu from the point's temperature.  Partials use
+// the 11-slot layout of k_diag (slots 0-2; the others hold the identities) for k_diag_final.
+__device__ __forceinline__ void quad_point(const FluxParams& fp, double w, const double q[5],
+                                           const double (*gr)[3], double* acc) {
+  const double rho = q[0];
+  const double ir = 1.0 / rho;
+  const double U[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
+  const double p = (fp.gamma - 1.0) * (q[4] - 0.5 * rho * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]));
+  double du[3][3];  // du[a][d] = d U_a / d x_d
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) du[a][d] = (gr[1 + a][d] - U[a] * gr[0][d]) * ir;
+  const double wx = du[2][1] - du[1][2], wy = du[0][2] - du[2][0], wz = du[1][0] - du[0][1];
+  const double div = du[0][0] + du[1][1] + du[2][2];
+  const double mu = viscosity<double>(fp, p * ir);
+  acc[0] += w * 0.5 * rho * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]);
+  acc[1] += w * mu * (wx * wx + wy * wy + wz * wz);
+  acc[2] += w * mu * div * div;
+}
+
+__device__ __forceinline__ void quad_partials(double* part, double* acc) {
+  __shared__ double sh[11][BLK];
+  double val[11] = {acc[0], acc[1], acc[2], 0, 0, 0, 0, 0, 0, INFINITY, INFINITY};
+  block_reduce<11>(sh, val, DiagOp{});
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 11; ++q) part[blockIdx.x * 11 + q] = val[q];
+}
+
+// CGKS-5th: C holds the coefficient blocks of the current state.  The nine (y, z) point pairs are
+// looped over; the three x points of a pair share one load of each variable's coefficients.
+template <class T>
+__global__ __launch_bounds__(BLK) void k_diag_quad5(Grid g, const double* __restrict__ Q,
+                                                    const T* __restrict__ C, FluxParams fp,
+                                                    double* part) {
+  using CB = CoefBlock<T>;
+  using V = typename Vec16<T>::type;
+  const int cell = blockIdx.x * BLK + threadIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (cell < g.N) {
+    const long long N = g.N;
+    double q0[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q0[v] = Q[v * N + cell];
+#pragma unroll 1
+    for (int s = 0; s < 9; ++s) {
+      double qv[3][5], gr[3][4][3];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const T* cb = C + CB::base(cell, v);
+        T a[CB::NBP];
+#pragma unroll
+        for (int c = 0; c < CB::NCH; ++c) {
+          const V x = *reinterpret_cast<const V*>(cb + c * CB::CHUNK_STRIDE);
+#pragma unroll
+          for (int e = 0; e < CB::PER; ++e) a[c * CB::PER + e] = x[e];
+        }
+#pragma unroll
+        for (int ix = 0; ix < 3; ++ix) {
+          const int qp = 3 * s + ix;
+          T val = T(0);
+#pragma unroll
+          for (int m = 0; m < tab::NB; ++m) val += a[m] * T(tab::PVQ[qp][m]);
+          qv[ix][v] = q0[v] + double(val);
+          if (v < 4) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+              T d = T(0);
+#pragma unroll
+              for (int m = 0; m < tab::NB; ++m)
+                if (tab::BD[m][e] > 0) d += a[m] * T(tab::PDQ[qp][e][m]);
+              gr[ix][v][e] = double(d) * g.ih[e];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int ix = 0; ix < 3; ++ix) quad_point(fp, tab::VQ_W[3 * s + ix], qv[ix], gr[ix], acc);
+    }
+  }
+  quad_partials(part, acc);
+}
+
+// GKS-2nd: S[(v * 3 + e) * N + cell] = the limited slope of variable v along axis e per unit of the
+// normalised coordinate; the gradient is constant over the cell.
+template <class T>
+__global__ __launch_bounds__(BLK) void k_diag_quad2(Grid g, const double* __restrict__ Q,
+                                                    const T* __restrict__ S, FluxParams fp,
+                                                    double* part) {
+  const int cell = blockIdx.x * BLK + threadIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (cell < g.N) {
+    const long long N = g.N;
+    double q0[5], sl[5][3], gr[4][3];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      q0[v] = Q[v * N + cell];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) sl[v][e] = double(S[(v * 3 + e) * N + cell]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) gr[v][e] = sl[v][e] * g.ih[e];
+#pragma unroll 1
+    for (int qp = 0; qp < tab::NVQ; ++qp) {
+      double q[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        q[v] = q0[v] + sl[v][0] * tab::VQ_X[qp][0] + sl[v][1] * tab::VQ_X[qp][1] + sl[v][2] * tab::VQ_X[qp][2];
+      quad_point(fp, tab::VQ_W[qp], q, gr, acc);
+    }
+  }
+  quad_partials(part, acc);
 }
 
 // ============================================================================ conversions

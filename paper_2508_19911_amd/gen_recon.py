@@ -12,8 +12,9 @@ Cartesian cell in normalised coordinates (delta = (x - x0)/h on [-1/2, 1/2]^3):
   data of every stencil cell).
 
 The solution a = R d is linear in the 75 data; R is emitted with the basis values and derivatives
-at the 2x2 Gauss points of the six faces (exact in Q(sqrt 3)) and the Gram matrix of the
-higher-order smoothness indicator sum_{1<=|alpha|<=4} int (D^alpha P)^2.  Output:
+at the 2x2 Gauss points of the six faces (exact in Q(sqrt 3)), at the 3x3x3 Gauss-Legendre points
+of the cell (for the quadrature of the diagnostics), and the Gram matrix of the higher-order
+smoothness indicator sum_{1<=|alpha|<=4} int (D^alpha P)^2.  Output:
 ``csrc/recon_tables.hpp``.  Run: ``python -m paper_2508_19911_amd.gen_recon``.
 """
 from __future__ import annotations
@@ -180,6 +181,51 @@ def basis_tables():
     return PV, PD
 
 
+# ---- 3x3x3 Gauss-Legendre points of the cell (volume quadrature of the diagnostics) ----------------
+# abscissae 0, +-sqrt(15)/10 on [-1/2, 1/2], weights 4/9 and 5/18 (exact for degree 5 per axis)
+VQ_ABS = [-1, 0, 1]          # multiples of sqrt(15)/10
+VQ_W1 = [Fr(5, 18), Fr(4, 9), Fr(5, 18)]
+
+
+def _dec(fr):
+    return decimal.Decimal(fr.numerator) / decimal.Decimal(fr.denominator)
+
+
+def volume_tables():
+    """Points (x fastest), weights, basis values p_m and derivatives d p_m / d delta_e at the 27 points."""
+    with decimal.localcontext() as ctx:
+        ctx.prec = 60
+        r = decimal.Decimal(15).sqrt() / 10
+        pts, wts, PVQ, PDQ = [], [], [], []
+        for kz in range(3):
+            for ky in range(3):
+                for kx in range(3):
+                    x = [VQ_ABS[kx] * r, VQ_ABS[ky] * r, VQ_ABS[kz] * r]
+                    pts.append([float(v) for v in x])
+                    wts.append(float(_dec(VQ_W1[kx] * VQ_W1[ky] * VQ_W1[kz])))
+
+                    def mono(d):
+                        v = decimal.Decimal(1)
+                        for k in range(3):
+                            if d[k]:
+                                v *= x[k] ** d[k] / factorial(d[k])
+                        return v
+                    PVQ.append([float(mono(d) - _dec(CELL_MEAN[j])) for j, d in enumerate(BASIS)])
+                    der = []
+                    for e in range(3):
+                        row = []
+                        for d in BASIS:
+                            if d[e] == 0:
+                                row.append(0.0)
+                            else:
+                                dd = list(d)
+                                dd[e] -= 1
+                                row.append(float(mono(dd)))
+                        der.append(row)
+                    PDQ.append(der)
+    return pts, wts, PVQ, PDQ
+
+
 def gram():
     def cell_int(n):  # integral of x^n over [-1/2,1/2]
         return Fr(0) if n % 2 else Fr(2, n + 1) * Fr(1, 2) ** (n + 1)
@@ -244,6 +290,20 @@ def generate() -> str:
     for f in range(6):
         L.append("  {" + ", ".join("{" + ", ".join("{" + ", ".join(fmt(v) for v in PD[f][k][e]) + "}"
                                                  for e in range(3)) + "}" for k in range(4)) + "},")
+    L.append("};")
+    vp, vw, PVQ, PDQ = volume_tables()
+    L.append("// 3x3x3 Gauss-Legendre points of the cell (x fastest): normalised coordinates, weights (sum 1),")
+    L.append("// PVQ[q][m] = p_m there, PDQ[q][e][m] = d p_m / d delta_e there")
+    L.append("constexpr int NVQ = 27;")
+    L.append("constexpr double VQ_X[27][3] = {" + ", ".join("{" + ", ".join(fmt(v) for v in x) + "}" for x in vp) + "};")
+    L.append("constexpr double VQ_W[27] = {" + ", ".join(fmt(v) for v in vw) + "};")
+    L.append("constexpr double PVQ[27][34] = {")
+    for q in range(27):
+        L.append("  {" + ", ".join(fmt(v) for v in PVQ[q]) + "},")
+    L.append("};")
+    L.append("constexpr double PDQ[27][3][34] = {")
+    for q in range(27):
+        L.append("  {" + ", ".join("{" + ", ".join(fmt(v) for v in PDQ[q][e]) + "}" for e in range(3)) + "},")
     L.append("};")
     L.append("// IS_H = a^T GR a, GR[i][j] = sum_{1<=|alpha|<=4} int_cell D^alpha p_i D^alpha p_j")
     L.append("constexpr double GR[34][34] = {")

@@ -158,6 +158,27 @@ def test_diagnostics_fp64():
         assert abs(dg[k] - do[k]) <= 1e-12 * do["mass"]
 
 
+@pytest.mark.parametrize("scheme,recon", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_diagnostics_quadrature(scheme, recon, precision):
+    """cgks_diagnostics_quad against the oracle's quadrature diagnostics on a seeded state of a ragged
+    13x7x5 grid (two blocks of the reduction): FP64 to 1e-12 relative; the FP32-bulk form (FP32
+    gradients and coefficients) to 1e-6 for E_k and 2e-5 for the dissipation rates."""
+    case, st = make_state("ragged_viscous")
+    case = case.with_(scheme=scheme, recon=recon)
+    o, s = pair(case, st, precision=precision)
+    do = o.diagnostics(1.0, 1.0, quad=True)
+    dg = s.diagnostics(1.0, 1.0, quad=True)
+    d1 = s.diagnostics(1.0, 1.0)
+    bars = {"Ek": 1e-12, "epsS": 1e-12, "epsD": 1e-12, "epsT": 1e-12} if precision == 0 else \
+        {"Ek": 1e-6, "epsS": 2e-5, "epsD": 2e-5, "epsT": 2e-5}
+    for k, bar in bars.items():
+        assert abs(dg[k] - do[k]) <= bar * abs(do[k]), (k, dg[k], do[k])
+    assert dg["Ek"] != d1["Ek"] and dg["mass"] == d1["mass"]
+    # the state is unchanged: a second call gives the same numbers
+    assert s.diagnostics(1.0, 1.0, quad=True) == dg
+
+
 def test_fp32_bulk_against_oracle():
     """FP32-bulk: float rounding of the flux (~2^-24 of the largest flux component) divided by h sets
     the error of one stage operator; after a few steps the state error stays at that level."""

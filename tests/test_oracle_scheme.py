@@ -234,3 +234,58 @@ def test_stage_at_cells_equals_whole_grid_stage(recon):
     part = o.stage_cells(dt, cells)
     for a, b in zip(full, part):
         assert np.array_equal(a[:, cells], b)
+
+
+@pytest.mark.parametrize("recon", [0, 1])
+def test_quadrature_diagnostics_converge_at_high_order(recon):
+    """Sec. 4.1, 4.2 integrate E_k and eps_S by quadrature of the reconstruction.  On the Taylor-Green
+    initial field the 3x3x3 Gauss rule over the fifth-order P^4 converges to E_k = 1/8 and
+    eps_S = (3/4)/Re at high order (E_k about h^6, eps_S, a derivative, about h^4), where the one-point
+    form converges at second order; eps_D stays 0 (solenoidal field); the box totals are the one-point
+    ones."""
+    errs = []
+    for n in (16, 32):
+        case = inputs.tgv_case(n, ma=0.01).with_(recon=recon)
+        q, g = inputs.tgv_state(case)
+        o = make(case); o.set_state(q, g)
+        d1, dq = o.diagnostics(), o.diagnostics(quad=True)
+        errs.append((dq["Ek"] - 0.125, dq["epsS"] / (0.75 * case.mu0) - 1))
+        for k in ("mass", "momx", "momy", "momz", "energy", "rho_min", "p_min"):
+            assert dq[k] == d1[k]
+        assert dq["epsD"] <= 1e-7 * dq["epsS"]
+        assert abs(dq["epsT"] - dq["epsS"] - dq["epsD"]) <= 1e-15 * dq["epsT"]
+    (ek16, es16), (ek32, es32) = errs
+    assert abs(ek32) < 1e-6 and abs(ek16 / ek32) > 30, errs
+    assert abs(es32) < 5e-4 and abs(es16 / es32) > 12, errs
+
+
+@pytest.mark.parametrize("scheme,recon", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_quadrature_diagnostics_of_a_uniform_flow(scheme, recon):
+    """A uniform state: every point of every cell carries (1/2) rho |U|^2 and no velocity gradient, so
+    the quadrature (weights summing to 1) returns E_k = (1/2) rho |U|^2 / (rho0 u0^2) and zero
+    dissipation exactly."""
+    case = inputs.tgv_case(5).with_(scheme=scheme, recon=recon, nx=5, ny=4, nz=3, ly=1.7, lz=0.9)
+    q, g = inputs.uniform_state(case, rho=1.3, u=(0.3, -0.2, 0.1), p=2.0)
+    o = make(case); o.set_state(q, g)
+    dq = o.diagnostics(quad=True)
+    assert abs(dq["Ek"] - 0.5 * 1.3 * 0.14) <= 1e-15
+    assert dq["epsS"] == 0.0 and dq["epsD"] == 0.0
+
+
+@pytest.mark.parametrize("recon", [0, 1])
+def test_quadrature_diagnostics_gks2(recon):
+    """GKS-2nd: the quadrature runs over its P^1 (central slopes, limited for NONLINEAR).  On the
+    Taylor-Green field E_k converges faster than the one-point form (the linear variation inside a
+    cell is integrated), and with the unlimited slopes eps_S keeps the one-point value of the central
+    differences to the variation of mu, rho and U over the cell (about h^2)."""
+    errs = []
+    for n in (16, 32):
+        case = inputs.tgv_case(n, ma=0.01).with_(scheme=1, recon=recon)
+        q, g = inputs.tgv_state(case)
+        o = make(case); o.set_state(q, g)
+        d1, dq = o.diagnostics(), o.diagnostics(quad=True)
+        errs.append(dq["Ek"] - 0.125)
+        assert abs(dq["Ek"] - 0.125) < 0.2 * abs(d1["Ek"] - 0.125)
+        if recon == 0:
+            assert abs(dq["epsS"] / d1["epsS"] - 1) < 1e-5
+    assert abs(errs[0] / errs[1]) > 7, errs
