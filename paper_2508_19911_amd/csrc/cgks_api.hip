@@ -168,7 +168,7 @@ int run_flags(Ctx& c, const double* Q, const T* G) {
 
 template <class T>
 int launch_coef(Ctx& c, const double* Q, const T* G) {
-  const dim3 grid(c.nblk, 5), blk(BLK);  // y: the conservative variable
+  const dim3 grid(coef_blocks(c.g), 5), blk(BLK);  // y: the conservative variable
   T* C = c.at<T>(c.L.C);
   const unsigned char* fl = c.at<unsigned char>(c.L.flags);
   TimedScope ts(c, CGKS_KC_COEF);
@@ -307,7 +307,7 @@ int diag_quad(Ctx& c, double* r) {
   if (c.p.scheme == CGKS_SCHEME_CGKS5) {
     const T* G = c.at<T>(c.L.G);
     const unsigned char* fl = c.at<unsigned char>(c.L.flags);
-    const dim3 cgrid(c.nblk, 5);
+    const dim3 cgrid(coef_blocks(c.g), 5);
     if (c.p.recon == CGKS_RECON_LINEAR)
       k_coef<T, 0><<<cgrid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp);
     else  // GENO everywhere (also for the learned form)

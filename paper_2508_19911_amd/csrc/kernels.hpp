@@ -148,35 +148,76 @@ __host__ __device__ __forceinline__ void gather_coefficients(const Grid& g, cons
   gather_step<T, 0>(g, qa, ga, oq, og, q0, q, gv, a, dface, g0);
 }
 
-// One thread per (cell, variable): blockIdx.y is the variable.  A thread's loads all precede its
-// stores, so no load waits behind the completion of earlier coefficient stores (loads and stores
-// share one completion counter, in issue order).
+// One thread per (cell, variable): blockIdx.y is the variable.  A block is a COEF_TX x COEF_TY x
+// COEF_TZ tile of cells (a wave = 64 consecutive x cells).  The block first stages the variable's
+// average and gradient planes over the tile and its one-cell halo in LDS, one coalesced load per
+// element (the 19-point gathers straight from memory issued 76 loads per cell, most of them L1
+// misses that held the vector-memory path waiting on L2); the stencil is then gathered from LDS.
+constexpr int COEF_TX = 64, COEF_TY = 2, COEF_TZ = 2;
+static_assert(COEF_TX * COEF_TY * COEF_TZ == BLK, "coefficient tile");
+constexpr int COEF_HX = COEF_TX + 2, COEF_HY = COEF_TY + 2, COEF_HZ = COEF_TZ + 2;
+constexpr int COEF_HALO = COEF_HX * COEF_HY * COEF_HZ;
+__host__ __device__ inline unsigned coef_blocks(const Grid& g) {
+  return (unsigned)(((g.nx + COEF_TX - 1) / COEF_TX) * ((g.ny + COEF_TY - 1) / COEF_TY) *
+                    ((g.nz + COEF_TZ - 1) / COEF_TZ));
+}
+
+// x >= -1 folded into [0, n): one step for a tile inside the grid, more only for grids smaller than
+// the tile
+__device__ __forceinline__ int wrap_into(int x, int n) {
+  if (x < 0) x += n;
+  while (x >= n) x -= n;
+  return x;
+}
+
+template <class T>
+struct CoefShared {
+  double q[COEF_HALO];     // the variable's averages over the tile and halo, x fastest
+  T gr[3][COEF_HALO];      // its three gradient components
+};
+
 template <class T, int MODE>  // MODE 0 linear, 1 GENO everywhere, 2 GENO where flagged
 __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__ Q,
                                               const T* __restrict__ G,
                                               const unsigned char* __restrict__ flags,
                                               T* __restrict__ C, GenoParams gp) {
-  const int cell = blockIdx.x * BLK + threadIdx.x;
+  __shared__ CoefShared<T> sh;
   const int v = blockIdx.y;
-  if (cell >= g.N) return;
-  int i, j, k;
-  cell_ijk(g, cell, i, j, k);
+  const int nbx = (g.nx + COEF_TX - 1) / COEF_TX, nby = (g.ny + COEF_TY - 1) / COEF_TY;
+  const int b = blockIdx.x;
+  const int i0 = (b % nbx) * COEF_TX, j0 = ((b / nbx) % nby) * COEF_TY, k0 = (b / (nbx * nby)) * COEF_TZ;
   const long long N = g.N;
-  // byte offsets of the 19 stencil cells in a plane of double and in a plane of T
+  const double* Qv = Q + v * N;
+  const T* Gv[3] = {G + v * N, G + (5 + v) * N, G + (10 + v) * N};
+  // stage the tile and its halo (periodic wrap; a tile past the grid edge wraps too)
+  for (int e = threadIdx.x; e < COEF_HALO; e += BLK) {
+    const int hx = e % COEF_HX, hy = (e / COEF_HX) % COEF_HY, hz = e / (COEF_HX * COEF_HY);
+    const int gi = wrap_into(i0 - 1 + hx, g.nx), gj = wrap_into(j0 - 1 + hy, g.ny), gk = wrap_into(k0 - 1 + hz, g.nz);
+    const uint32_t c = (uint32_t)((gk * g.ny + gj) * g.nx + gi);
+    sh.q[e] = ld(Qv, c);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sh.gr[d][e] = ld(Gv[d], c);
+  }
+  __syncthreads();
+  const int tx = (int)(threadIdx.x % COEF_TX), ty = (int)(threadIdx.x / COEF_TX) % COEF_TY,
+            tz = (int)(threadIdx.x / (COEF_TX * COEF_TY));
+  const int i = i0 + tx, j = j0 + ty, k = k0 + tz;
+  if (i >= g.nx || j >= g.ny || k >= g.nz) return;
+  const int cell = (k * g.ny + j) * g.nx + i;
+  // byte offsets of the 19 stencil cells in the staged planes of double and of T
   uint32_t oq[tab::NSTEN], og[tab::NSTEN];
 #pragma unroll
   for (int s = 0; s < tab::NSTEN; ++s) {
-    const uint32_t c = (uint32_t)((wrap_o(k, tab::SOFF[s][2], g.nz) * g.ny + wrap_o(j, tab::SOFF[s][1], g.ny)) *
-                                      g.nx + wrap_o(i, tab::SOFF[s][0], g.nx));
-    oq[s] = c * 8u;
-    og[s] = c * (uint32_t)sizeof(T);
+    const uint32_t e = (uint32_t)(((tz + 1 + tab::SOFF[s][2]) * COEF_HY + (ty + 1 + tab::SOFF[s][1])) * COEF_HX +
+                                  (tx + 1 + tab::SOFF[s][0]));
+    oq[s] = e * 8u;
+    og[s] = e * (uint32_t)sizeof(T);
   }
   bool geno = MODE == 1;
   if constexpr (MODE == 2) geno = flags[cell] != 0;
-  const BufPlane<double> qa(Q + v * N, N);
-  const BufPlane<T> ga[3] = {BufPlane<T>(G + v * N, N), BufPlane<T>(G + (5 + v) * N, N),
-                             BufPlane<T>(G + (10 + v) * N, N)};
-  const double q0 = ld(Q + v * N, (uint32_t)cell);
+  const PtrPlane<double> qa{sh.q};
+  const PtrPlane<T> ga[3] = {PtrPlane<T>{sh.gr[0]}, PtrPlane<T>{sh.gr[1]}, PtrPlane<T>{sh.gr[2]}};
+  const double q0 = sh.q[((tz + 1) * COEF_HY + (ty + 1)) * COEF_HX + (tx + 1)];
   T a[tab::NB], dface[6], g0[3];
 #pragma unroll
   for (int m = 0; m < tab::NB; ++m) a[m] = T(0);
