@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # write), from two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE) scaled by a 1 GiB copy
 # kernel: profiles/flux_tgv128_hbm_counters.md.  Valid only for the kernel sources they were taken
 # on; any change to those sources makes the reported traffic null until the counters are retaken.
-FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8647e+09,
-                "sources_sha256": "8aa9a2e53278e54b3dca4e0a81a13f55d6347f51ebc4582b8d22ca1d1ec71079"}
+FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8650e+09,
+                "sources_sha256": "04258d698c1e03f300fad3a2dfec46926f7274a6dbd8dc1897ffba75facd551b"}
 KERNEL_SOURCES = ["common.hpp", "gks_flux.hpp", "recon.hpp", "recon_tables.hpp", "kernels.hpp"]
 
 

@@ -184,7 +184,9 @@ __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__
   __shared__ CoefShared<T> sh;
   const int v = blockIdx.y;
   const int nbx = (g.nx + COEF_TX - 1) / COEF_TX, nby = (g.ny + COEF_TY - 1) / COEF_TY;
-  const int b = blockIdx.x;
+  // contiguous tile ranges per XCD: the halo rows a tile shares with its y and z neighbours (2 and
+  // 2 nbx nby tiles away) are then read through the same L2
+  const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
   const int i0 = (b % nbx) * COEF_TX, j0 = ((b / nbx) % nby) * COEF_TY, k0 = (b / (nbx * nby)) * COEF_TZ;
   const long long N = g.N;
   const double* Qv = Q + v * N;
@@ -258,8 +260,10 @@ struct FluxShared {
   T D[FLUX_FACES][4][10][3];     // face-frame derivatives, physical units
 };
 
+// FP64 asks for two waves per SIMD: it then spills a few registers to scratch but runs 1.12x faster
+// than at one wave with every value in registers (measured at 128^3).
 template <class T, int DIR>
-__global__ __launch_bounds__(FLUX_BLK) void k_flux5(Grid g, const double* __restrict__ Q,
+__global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 2 : 1) void k_flux5(Grid g, const double* __restrict__ Q,
                                                     const T* __restrict__ C, T* __restrict__ F,
                                                     FluxParams fp, double dt) {
   __shared__ FluxShared<T> sh;

@@ -81,6 +81,7 @@ __device__ __forceinline__ void cell_features(const Grid& g, const double* __res
   double q5[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) q5[v] = Q[v * N + cell];
+  double mx_line[2];  // the maximum of feature 54 + v for v = 0, 4, found on the way
 #pragma unroll
   for (int vi = 0; vi < 2; ++vi) {
     const int v = vi ? 4 : 0;
@@ -103,6 +104,7 @@ __device__ __forceinline__ void cell_features(const Grid& g, const double* __res
         mxg = fmax(mxg, fabs(gg));
       }
     }
+    mx_line[vi] = fmax(mxd, mxg);
     const double is = 1.0 / (mxd + mxg + 1e-12 * fabs(q0));
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -117,15 +119,18 @@ __device__ __forceinline__ void cell_features(const Grid& g, const double* __res
   const double hmax = fmax(g.h[0], fmax(g.h[1], g.h[2]));
 #pragma unroll 1
   for (int v = 0; v < 5; ++v) {
-    const BufPlane<double> qv(Q + v * N, N);
-    double mx = 0.0;
+    double mx = v == 0 ? mx_line[0] : mx_line[1];
+    if (v != 0 && v != 4) {  // the momenta: their lines were not read above
+      const BufPlane<double> qv(Q + v * N, N);
+      mx = 0.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const BufPlane<T> gd(G + (d * 5 + v) * N, N);
+      for (int d = 0; d < 3; ++d) {
+        const BufPlane<T> gd(G + (d * 5 + v) * N, N);
 #pragma unroll
-      for (int o = 0; o < 5; ++o) {
-        mx = fmax(mx, fabs(qv(oq[d][o]) - q5[v]));
-        mx = fmax(mx, fabs(g.h[d] * double(gd(og[d][o]))));
+        for (int o = 0; o < 5; ++o) {
+          mx = fmax(mx, fabs(qv(oq[d][o]) - q5[v]));
+          mx = fmax(mx, fabs(g.h[d] * double(gd(og[d][o]))));
+        }
       }
     }
     // the ratio in FP64, its logarithm in FP32 (a feature needs no more)
