@@ -50,6 +50,19 @@ struct FrameMom {
   T u[7], vu[4], ph[4], qq[3], vh[2];
 };
 
+// sqrt(lam) and sqrt(var) = sqrt(1 / (2 lam)); the FP32 form takes both from one reciprocal square
+// root
+template <class T>
+__host__ __device__ __forceinline__ void lam_roots(T lam, T var, T& sl, T& sv) {
+  sl = dsqrt(lam);
+  sv = dsqrt(var);
+}
+__host__ __device__ __forceinline__ void lam_roots(float lam, float, float& sl, float& sv) {
+  const float r = drsq(lam);
+  sl = lam * r;
+  sv = 0.70710678118654752f * r;
+}
+
 // normal moments by the Gaussian recursion u_k = U u_{k-1} + (k-1) var u_{k-2} (exact on a half
 // range bounded at 0 once k >= 2); HALF = +1 (u > 0), -1 (u < 0) or 0 (full range)
 template <int HALF, class T>
@@ -59,9 +72,10 @@ __host__ __device__ __forceinline__ void frame_moments(const Prim<T>& p, T Kdof,
     m.u[0] = T(1);
     m.u[1] = p.U;
   } else {
-    const T sl = dsqrt(p.lam);
+    T sl, sv;
+    lam_roots(p.lam, var, sl, sv);
     // e^{-lam U^2} / (2 sqrt(pi lam)) = e^{-lam U^2} sqrt(var / (2 pi))
-    const T tail = dexp(-p.lam * p.U * p.U) * (T(0.39894228040143267794) * dsqrt(var));
+    const T tail = dexp(-p.lam * p.U * p.U) * (T(0.39894228040143267794) * sv);
     if constexpr (HALF > 0) {
       m.u[0] = T(0.5) * derfc(-sl * p.U);
       m.u[1] = p.U * m.u[0] + tail;
