@@ -322,17 +322,14 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
 #pragma unroll
     for (int d = 0; d < 3; ++d) tslope<0, true>(mh, b[d], dw[d]);
     {
-      T Vb[5], Wb[5];
+      // the lab-velocity parts V b1 + W b2 of the tangential transport share one product
+      T VW[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        Vb[v] = V * b[1][v];
-        Wb[v] = W * b[2][v];
-      }
+      for (int v = 0; v < 5; ++v) VW[v] = V * b[1][v] + W * b[2][v];
       tslope<2, true>(mh, b[0], s1);
       tslope_t<1, 2>(mh, b[1], s1);
-      tslope<1>(mh, Vb, s1);
       tslope_t<1, 3>(mh, b[2], s1);
-      tslope<1>(mh, Wb, s1);
+      tslope<1>(mh, VW, s1);
     }
     tslope<1, true>(mh, B, s2);
     tslope<1, true>(mh, b[0], s4);
@@ -406,17 +403,13 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
     T g0[5], g1[5], g2[5];
     tpsi<1>(m0, p0.rho, g0);
     {
-      T Vb[5], Wb[5];
+      T VW[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        Vb[v] = V * bb[1][v];
-        Wb[v] = W * bb[2][v];
-      }
+      for (int v = 0; v < 5; ++v) VW[v] = V * bb[1][v] + W * bb[2][v];
       tslope<2, true>(m0, bb[0], g1);
       tslope_t<1, 2>(m0, bb[1], g1);
-      tslope<1>(m0, Vb, g1);
       tslope_t<1, 3>(m0, bb[2], g1);
-      tslope<1>(m0, Wb, g1);
+      tslope<1>(m0, VW, g1);
     }
     tslope<1, true>(m0, Bb, g2);
     from_frame<true, true>(g0, V, W, kv, G[0]);

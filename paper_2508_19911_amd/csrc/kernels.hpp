@@ -71,70 +71,83 @@ struct CoefBlock {
 };
 
 // ============================================================================ reconstruction
-// Gather the stencil of one variable and accumulate a = R d column by column; the face-neighbour
-// differences and the cell's own normalised gradient are kept for GENO.  qa reads the variable's
-// average plane and ga[3] its three gradient planes; oq[s], og[s] are the byte offsets of stencil
-// cell s in a plane of double and of T.
-//
-// The stencil cells are taken one at a time in a software pipeline: the loads of the cell
-// GATHER_AHEAD positions later are issued before a cell is accumulated, so a lane keeps
-// GATHER_AHEAD cells of loads in flight (a full hoist of all 19 cells' loads would not fit the
-// register budget).
-#ifndef CGKS_GATHER_AHEAD
-#define CGKS_GATHER_AHEAD 2
-#endif
-constexpr int GATHER_AHEAD = CGKS_GATHER_AHEAD;
-static_assert(GATHER_AHEAD >= 1 && GATHER_AHEAD < tab::NSTEN, "gather pipeline depth");
+// a = R d for one variable of one cell, over the reflection orbits of the data columns: each orbit's
+// data are loaded, combined into their sign-pattern sums D_k, and a[m] += RS[m][k] D_k (216 FMAs and
+// the pattern sums instead of the 678 of R).  The face-neighbour differences and the cell's own
+// normalised gradient are kept for GENO.  qa reads the variable's averages and ga[3] its gradient
+// components; oq[s], og[s] are the byte offsets of stencil cell s for qa and for ga.
 
-template <int S, class T, class QA, class GA>
-__host__ __device__ __forceinline__ void gather_load(const QA& qa, const GA* ga, const uint32_t* oq,
-                                                     const uint32_t* og, double* q, T (*gv)[3]) {
-  if constexpr (S < tab::NSTEN) {
-    if constexpr (S != tab::CENTRE) q[S] = qa(oq[S]);
-#pragma unroll
-    for (int e = 0; e < 3; ++e) gv[S][e] = ga[e](og[S]);
+// stencil index of neighbour slot n (the data column of its value difference)
+constexpr int stencil_of_slot(int n) {
+  for (int s = 0; s < tab::NSTEN; ++s)
+    if (tab::NEIGH_SLOT[s] == n) return s;
+  return -1;
+}
+
+// datum of data column C: Q(neighbour) - Q0 for C < 18, else h_e dQ/dx_e of a stencil cell
+template <int C, class T, class QA, class GA>
+__host__ __device__ __forceinline__ T column_datum(const Grid& g, const QA& qa, const GA* ga,
+                                                   const uint32_t* oq, const uint32_t* og, double q0) {
+  if constexpr (C < 18) {
+    constexpr int S = stencil_of_slot(C);
+    static_assert(S >= 0, "neighbour slot");
+    return data<T>(qa(oq[S]) - q0);
+  } else {
+    constexpr int S = (C - 18) / 3, E = (C - 18) % 3;
+    return T(g.h[E]) * ga[E](og[S]);
   }
 }
 
-template <class T, int S, class QA, class GA>
-__host__ __device__ __forceinline__ void gather_step(const Grid& g, const QA& qa, const GA* ga,
-                                                     const uint32_t* oq, const uint32_t* og, double q0,
-                                                     double* q, T (*gv)[3], T* a, T* dface, T* g0) {
-  if constexpr (S < tab::NSTEN) {
-    gather_load<S + GATHER_AHEAD, T>(qa, ga, oq, og, q, gv);
-#ifdef __HIP_DEVICE_COMPILE__
-    // the scheduler keeps this order: the loads GATHER_AHEAD cells ahead, then the columns of cell S
-    __builtin_amdgcn_sched_barrier(0);
-#endif
-    if constexpr (S != tab::CENTRE) {
-      const T x = data<T>(q[S] - q0);
-      op_col<tab::NEIGH_SLOT[S]>(x, a);
-#pragma unroll
-      for (int f = 0; f < 6; ++f)
-        if (face_slot(f) == tab::NEIGH_SLOT[S]) dface[f] = x;
-    }
-    const T gx = T(g.h[0]) * gv[S][0], gy = T(g.h[1]) * gv[S][1], gz = T(g.h[2]) * gv[S][2];
-    op_col<18 + 3 * S + 0>(gx, a);
-    op_col<18 + 3 * S + 1>(gy, a);
-    op_col<18 + 3 * S + 2>(gz, a);
-    if constexpr (S == tab::CENTRE) {
-      g0[0] = gx;
-      g0[1] = gy;
-      g0[2] = gz;
-    }
-#ifdef __HIP_DEVICE_COMPILE__
-    __builtin_amdgcn_sched_barrier(0);
-#endif
-    gather_step<T, S + 1>(g, qa, ga, oq, og, q0, q, gv, a, dface, g0);
+template <int K, int N, class T>
+__host__ __device__ __forceinline__ T pattern_sum(const T* x) {
+  T d = tab::PAT_SIGN[K][0] > 0 ? x[0] : -x[0];
+  if constexpr (N > 1) d = tab::PAT_SIGN[K][1] > 0 ? d + x[1] : d - x[1];
+  if constexpr (N > 2) d = tab::PAT_SIGN[K][2] > 0 ? d + x[2] : d - x[2];
+  if constexpr (N > 3) d = tab::PAT_SIGN[K][3] > 0 ? d + x[3] : d - x[3];
+  return d;
+}
+
+template <int K, class T, int... M>
+__host__ __device__ __forceinline__ void rs_column(T d, T* a, std::integer_sequence<int, M...>) {
+  ((tab::RS[M][K] != 0.0 ? (void)(a[M] = dfma(T(tab::RS[M][K]), d, a[M])) : (void)0), ...);
+}
+
+template <int O, int K, class T>
+__host__ __device__ __forceinline__ void orbit_patterns(const T* x, T* a) {
+  if constexpr (K < tab::ORB_PAT0[O] + tab::ORB_NPAT[O]) {
+    rs_column<K>(pattern_sum<K, tab::ORB_SIZE[O]>(x), a, std::make_integer_sequence<int, tab::NB>{});
+    orbit_patterns<O, K + 1>(x, a);
   }
 }
 
-template <class T, int P = 0, class QA, class GA>
-__host__ __device__ __forceinline__ void gather_prologue(const QA& qa, const GA* ga, const uint32_t* oq,
-                                                         const uint32_t* og, double* q, T (*gv)[3]) {
-  if constexpr (P < GATHER_AHEAD) {
-    gather_load<P, T>(qa, ga, oq, og, q, gv);
-    gather_prologue<T, P + 1>(qa, ga, oq, og, q, gv);
+// the member R of orbit O: its datum, also kept for GENO when it is a face difference or the
+// cell's own gradient
+template <int O, int R, class T, class QA, class GA>
+__host__ __device__ __forceinline__ void orbit_member(const Grid& g, const QA& qa, const GA* ga,
+                                                      const uint32_t* oq, const uint32_t* og, double q0,
+                                                      T* x, T* dface, T* g0) {
+  if constexpr (R < tab::ORB_SIZE[O]) {
+    constexpr int C = tab::ORB_COL[O][R];
+    x[R] = column_datum<C, T>(g, qa, ga, oq, og, q0);
+#pragma unroll
+    for (int f = 0; f < 6; ++f)
+      if (C == face_slot(f)) dface[f] = x[R];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+      if (C == 18 + 3 * tab::CENTRE + e) g0[e] = x[R];
+    orbit_member<O, R + 1>(g, qa, ga, oq, og, q0, x, dface, g0);
+  }
+}
+
+template <class T, int O, class QA, class GA>
+__host__ __device__ __forceinline__ void gather_orbits(const Grid& g, const QA& qa, const GA* ga,
+                                                       const uint32_t* oq, const uint32_t* og, double q0,
+                                                       T* a, T* dface, T* g0) {
+  if constexpr (O < tab::NORB) {
+    T x[4];
+    orbit_member<O, 0>(g, qa, ga, oq, og, q0, x, dface, g0);
+    orbit_patterns<O, tab::ORB_PAT0[O]>(x, a);
+    gather_orbits<T, O + 1>(g, qa, ga, oq, og, q0, a, dface, g0);
   }
 }
 
@@ -142,10 +155,7 @@ template <class T, class QA, class GA>
 __host__ __device__ __forceinline__ void gather_coefficients(const Grid& g, const QA& qa, const GA* ga,
                                                              const uint32_t* oq, const uint32_t* og,
                                                              double q0, T* a, T* dface, T* g0) {
-  double q[tab::NSTEN];
-  T gv[tab::NSTEN][3];
-  gather_prologue<T>(qa, ga, oq, og, q, gv);
-  gather_step<T, 0>(g, qa, ga, oq, og, q0, q, gv, a, dface, g0);
+  gather_orbits<T, 0>(g, qa, ga, oq, og, q0, a, dface, g0);
 }
 
 // One thread per (cell, variable): blockIdx.y is the variable.  A block is a COEF_TX x COEF_TY x

@@ -279,6 +279,25 @@ def generate() -> str:
     L.append("};")
     nnz = sum(1 for i in range(NB) for v in R[i] if v != 0)
     L.append(f"constexpr int R_NNZ = {nnz};")
+    orbits, patterns, RS = orbit_tables(R)
+    L.append("// reflection orbits of the data columns (members, -1 unused), their sign patterns (each a run")
+    L.append("// of patterns per orbit) and the reduced operator: a[m] += RS[m][k] * sum_r PAT_SIGN[k][r] d[ORB_COL[o][r]]")
+    L.append(f"constexpr int NORB = {len(orbits)};")
+    L.append(f"constexpr int NPAT = {len(patterns)};")
+    L.append("constexpr int ORB_SIZE[NORB] = {" + ", ".join(str(len(o)) for o in orbits) + "};")
+    L.append("constexpr int ORB_COL[NORB][4] = {" + ", ".join(
+        "{" + ", ".join(str(c) for c in (o + [-1] * (4 - len(o)))) + "}" for o in orbits) + "};")
+    first = [next(k for k, p in enumerate(patterns) if p[0] == o) for o in range(len(orbits))]
+    count = [sum(1 for p in patterns if p[0] == o) for o in range(len(orbits))]
+    L.append("constexpr int ORB_PAT0[NORB] = {" + ", ".join(map(str, first)) + "};")
+    L.append("constexpr int ORB_NPAT[NORB] = {" + ", ".join(map(str, count)) + "};")
+    L.append("constexpr int PAT_SIGN[NPAT][4] = {" + ", ".join(
+        "{" + ", ".join(str(v) for v in (list(p[1]) + [0] * (4 - len(p[1])))) + "}" for p in patterns) + "};")
+    L.append("constexpr double RS[34][NPAT] = {")
+    for i in range(NB):
+        L.append("  {" + ", ".join(fmt(v) for v in RS[i]) + "},")
+    L.append("};")
+    L.append(f"constexpr int RS_NNZ = {sum(1 for i in range(NB) for v in RS[i] if v != 0)};")
     L.append("// faces f = (-x,+x,-y,+y,-z,+z); Gauss point k: tangential signs along ((e+1)%3, (e+2)%3)")
     L.append("constexpr int GP_SIGN[4][2] = {" + ", ".join("{%d,%d}" % s for s in GP_SIGNS) + "};")
     L.append("// PV[f][k][m] = p_m at Gauss point k of face f; PD[f][k][e][m] = d p_m / d delta_e there")
@@ -313,6 +332,71 @@ def generate() -> str:
     L.append("}  // namespace tab")
     L.append("}  // namespace cgks")
     return "\n".join(L) + "\n"
+
+
+# ---- reflection symmetry of the operator ----------------------------------------------------------
+# The stencil, the basis and the least-squares weights are invariant under the reflections x -> -x,
+# y -> -y, z -> -z, so R is equivariant: a column's image under a reflection g (the datum at the
+# reflected offset; a gradient component along a flipped axis changes sign) carries R[m][c] times the
+# basis function's parity chi_m(g).  Grouping the 75 columns into orbits, sum_c R[m][c] d_c becomes
+# sum over orbits of R[m][c0] D_{o,k(m)} with D_{o,k} = sum_{c in o} s_k(c) d_c: 216 FMAs and the
+# pattern sums instead of 678 FMAs.  Checked exactly here.
+def data_columns():
+    cols = [("v", o, -1) for o in NEIGH] + [("g", o, e) for o in STENCIL for e in range(3)]
+    return cols
+
+
+def orbit_tables(R=None):
+    """Orbits of the data columns, their sign patterns and the reduced operator (exact Fractions).
+    Returns (orbits: list of member-column lists, patterns: list of (orbit, signs), RS[m][k])."""
+    import itertools
+    R = R if R is not None else build_operator()
+    cols = data_columns()
+    index = {c: i for i, c in enumerate(cols)}
+    group = list(itertools.product((1, -1), repeat=3))
+
+    def image(c, g):
+        t, o, e = c
+        o2 = (g[0] * o[0], g[1] * o[1], g[2] * o[2])
+        return index[(t, o2, e)], (1 if t == "v" else g[e])
+
+    seen, orbits, maps = set(), [], []
+    for i, c in enumerate(cols):
+        if i in seen:
+            continue
+        mem = {}
+        for g in group:
+            j, sg = image(c, g)
+            mem.setdefault(j, (g, sg))
+        members = [i] + sorted(j for j in mem if j != i)
+        orbits.append(members)
+        maps.append(mem)
+        seen |= set(mem)
+    patterns, RS = [], [[Fr(0)] * 0 for _ in range(NB)]
+    rs_cols = []
+    for o, (members, mem) in enumerate(zip(orbits, maps)):
+        c0 = members[0]
+        pats = {}
+        for m in range(NB):
+            if all(R[m][j] == 0 for j in members):
+                continue
+            assert R[m][c0] != 0
+            d = BASIS[m]
+            sig = []
+            for j in members:
+                g, sg = mem[j]
+                sgn = g[0] ** d[0] * g[1] ** d[1] * g[2] ** d[2] * sg
+                assert R[m][j] == sgn * R[m][c0], (m, j)
+                sig.append(sgn)
+            pats.setdefault(tuple(sig), []).append(m)
+        for sig, ms in pats.items():
+            patterns.append((o, sig))
+            col = [Fr(0)] * NB
+            for m in ms:
+                col[m] = R[m][c0]
+            rs_cols.append(col)
+    RS = [[rs_cols[k][m] for k in range(len(rs_cols))] for m in range(NB)]
+    return orbits, patterns, RS
 
 
 def exact_operator():
