@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # write), from two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE) scaled by a 1 GiB copy
 # kernel: profiles/flux_tgv128_hbm_counters.md.  Valid only for the kernel sources they were taken
 # on; any change to those sources makes the reported traffic null until the counters are retaken.
-FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8650e+09,
-                "sources_sha256": "04258d698c1e03f300fad3a2dfec46926f7274a6dbd8dc1897ffba75facd551b"}
+FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8763e+09,
+                "sources_sha256": "8c2369ed6f773f3b5a7b93063a3537c8664f6279d1a690ae88b457d2d32d299d"}
 KERNEL_SOURCES = ["common.hpp", "gks_flux.hpp", "recon.hpp", "recon_tables.hpp", "kernels.hpp"]
 
 
