@@ -2,6 +2,7 @@
 // the per-step launch sequence of the CGKS-5th / GKS-2nd sweep on one MI355X.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -184,7 +185,7 @@ int launch_coef(Ctx& c, const double* Q, const T* G) {
 // one CGKS-5th stage on (Q, G); STAGE 0 debug, 1 first, 2 second.  The learned indicator runs once
 // per time step, on the first stage's input; the second stage keeps its flags.
 template <class T, int STAGE>
-int stage5(Ctx& c, const double* Q, const T* G, double dt) {
+int stage5(Ctx& c, const double* Q, const T* G, const double* ctl) {
   int rc = STAGE == 2 ? CGKS_OK : run_flags<T>(c, Q, G);
   if (rc) return rc;
   rc = launch_coef<T>(c, Q, G);
@@ -195,15 +196,15 @@ int stage5(Ctx& c, const double* Q, const T* G, double dt) {
   T* F = c.at<T>(c.L.F);
   {
     TimedScope t0(c, CGKS_KC_FLUX);
-    k_flux5<T, 0><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
+    k_flux5<T, 0><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, ctl);
   }
   {
     TimedScope t1(c, CGKS_KC_FLUX);
-    k_flux5<T, 1><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
+    k_flux5<T, 1><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, ctl);
   }
   {
     TimedScope t2(c, CGKS_KC_FLUX);
-    k_flux5<T, 2><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, dt);
+    k_flux5<T, 2><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, ctl);
   }
   LAUNCHCK("k_flux5");
   Stage5Out o;
@@ -215,14 +216,14 @@ int stage5(Ctx& c, const double* Q, const T* G, double dt) {
   o.G = c.at<T>(c.L.G);
   {
     TimedScope tu(c, CGKS_KC_UPDATE);
-    k_update5<T, STAGE><<<grid, blk, 0, c.stream>>>(c.g, F, c.at<double>(c.L.Q), o, dt);
+    k_update5<T, STAGE><<<grid, blk, 0, c.stream>>>(c.g, F, c.at<double>(c.L.Q), o, ctl);
   }
   LAUNCHCK("k_update5");
   return CGKS_OK;
 }
 
 template <class T, int DEBUG>
-int stage2(Ctx& c, double dt) {
+int stage2(Ctx& c, const double* ctl) {
   const dim3 grid(c.nblk), blk(BLK);
   double* Q = c.at<double>(c.L.Q);
   T* S = c.at<T>(c.L.C);
@@ -236,36 +237,49 @@ int stage2(Ctx& c, double dt) {
   }
   {
     TimedScope t0(c, CGKS_KC_FLUX);
-    k_flux2<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, dt);
+    k_flux2<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, ctl);
   }
   {
     TimedScope t1(c, CGKS_KC_FLUX);
-    k_flux2<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, dt);
+    k_flux2<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, ctl);
   }
   {
     TimedScope t2(c, CGKS_KC_FLUX);
-    k_flux2<T, 2><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, dt);
+    k_flux2<T, 2><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, ctl);
   }
   {
     TimedScope tu(c, CGKS_KC_UPDATE);
     k_update2<T, DEBUG><<<grid, blk, 0, c.stream>>>(c.g, F, Q, c.at<double>(c.L.Acc),
-                                                     c.at<double>(c.L.Qs), dt);
+                                                     c.at<double>(c.L.Qs), ctl);
   }
   LAUNCHCK("gks2 stage");
   return CGKS_OK;
 }
 
 template <class T>
-int advance(Ctx& c, double dt) {
+int advance(Ctx& c, const double* ctl) {
   int rc;
-  if (c.p.scheme == CGKS_SCHEME_GKS2) return stage2<T, 0>(c, dt);
-  rc = stage5<T, 1>(c, c.at<double>(c.L.Q), c.at<T>(c.L.G), dt);
+  if (c.p.scheme == CGKS_SCHEME_GKS2) return stage2<T, 0>(c, ctl);
+  rc = stage5<T, 1>(c, c.at<double>(c.L.Q), c.at<T>(c.L.G), ctl);
   if (rc) return rc;
-  return stage5<T, 2>(c, c.at<double>(c.L.Qs), c.at<T>(c.L.Gs), dt);
+  return stage5<T, 2>(c, c.at<double>(c.L.Qs), c.at<T>(c.L.Gs), ctl);
 }
 
-int advance_any(Ctx& c, double dt) {
-  return c.p.precision == CGKS_PREC_FP64 ? advance<double>(c, dt) : advance<float>(c, dt);
+int advance_any(Ctx& c, const double* ctl) {
+  return c.p.precision == CGKS_PREC_FP64 ? advance<double>(c, ctl) : advance<float>(c, ctl);
+}
+
+// steps queued between two read-backs of the device step control
+constexpr int STEP_BATCH = 8;
+
+// the step-control block on the device (after the 11 reduction results in the scalar area)
+double* step_ctl(Ctx& c) { return c.at<double>(c.L.scal) + 32; }
+
+// a host-chosen dt for the stage kernels
+const double* set_dt(Ctx& c, double dt) {
+  double* ctl = step_ctl(c);
+  k_ctl_set_dt<<<1, 64, 0, c.stream>>>(ctl, dt);
+  return ctl;
 }
 
 // dt limits: out[0] = min h/(|U|+c), out[1] = max nu, out[2] = non-physical flag
@@ -522,21 +536,50 @@ int cgks_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done,
   if (!c.have_state) rc = CGKS_ESTATE;
   else if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) rc = CGKS_ESTATE;
   else if (!(cfl > 0.0) || nsteps < 0) rc = CGKS_EINVAL;
-  for (; rc == CGKS_OK && done < nsteps; ++done) {
-    if (t_stop > 0.0 && c.t >= t_stop) break;
-    double lim[3];
-    rc = dt_limits(c, lim);
-    if (rc) break;
-    if (lim[2] != 0.0) {
-      rc = CGKS_ENONPHYSICAL;
-      break;
+  if (rc == CGKS_OK && nsteps > 0 && !(t_stop > 0.0 && c.t >= t_stop)) {
+    // Steps are queued in batches: dt, the t_stop shortening and the non-physical stop are decided
+    // on the device (k_step_control); the host reads t and the step count back once per batch.
+    double* ctl = step_ctl(c);
+    double* part = c.at<double>(c.L.red);
+    double* lim = c.at<double>(c.L.scal);
+    const double hmin = std::fmin(c.g.h[0], std::fmin(c.g.h[1], c.g.h[2]));
+    const int viscous = c.p.mu0 > 0.0 ? 1 : 0;
+    const double t0 = c.t;
+    k_ctl_init<<<1, 64, 0, c.stream>>>(ctl, t0);
+    int queued = 0;
+    double h[4] = {0.0, 0.0, t0, 0.0};
+    while (rc == CGKS_OK && queued < nsteps) {
+      const int batch = std::min(STEP_BATCH, nsteps - queued);
+      for (int b = 0; b < batch && rc == CGKS_OK; ++b) {
+        {
+          TimedScope ts(c, CGKS_KC_DT);
+          k_dt<<<c.nblk, BLK, 0, c.stream>>>(c.g, c.at<double>(c.L.Q), c.fp, part);
+          k_dt_final<<<1, BLK, 0, c.stream>>>(c.nblk, part, lim);
+          k_step_control<<<1, 64, 0, c.stream>>>(lim, ctl, cfl, hmin, viscous, t_stop);
+        }
+        LAUNCHCK("k_dt");
+        rc = advance_any(c, ctl);
+        if (rc == CGKS_OK) {
+          k_step_advance<<<1, 64, 0, c.stream>>>(ctl);
+          LAUNCHCK("k_step_advance");
+        }
+      }
+      queued += batch;
+      if (rc != CGKS_OK) break;
+      {
+        hipError_t e = hipMemcpyAsync(h, ctl, 4 * sizeof(double), hipMemcpyDeviceToHost, c.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+        if (e != hipSuccess) {
+          rc = dev_error("step control read-back", e);
+          break;
+        }
+      }
+      if (h[1] == 2.0) rc = CGKS_ENONPHYSICAL;
+      if (h[1] != 0.0) break;
     }
-    double dt = dt_from_limits(c, lim, cfl);
-    if (t_stop > 0.0 && c.t + dt > t_stop) dt = t_stop - c.t;
-    rc = advance_any(c, dt);
-    if (rc) break;
-    c.t += dt;
-    c.step += 1;
+    done = (int)h[3];
+    c.t = h[2];
+    c.step += done;
   }
   if (rc == CGKS_OK) {
     hipError_t e = hipStreamSynchronize(c.stream);
@@ -553,8 +596,9 @@ int cgks_step_fixed(void* ctx, int nsteps, double dt) {
   if (!c.have_state) return CGKS_ESTATE;
   if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) return CGKS_ESTATE;
   if (!(dt > 0.0) || nsteps < 0) return CGKS_EINVAL;
+  const double* ctl = set_dt(c, dt);
   for (int s = 0; s < nsteps; ++s) {
-    int rc = advance_any(c, dt);
+    int rc = advance_any(c, ctl);
     if (rc) return rc;
     c.t += dt;
     c.step += 1;
@@ -570,13 +614,14 @@ int cgks_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double*
   if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) return CGKS_ESTATE;
   if (!(dt > 0.0)) return CGKS_EINVAL;
   const bool f64 = c.p.precision == CGKS_PREC_FP64;
+  const double* ctl = set_dt(c, dt);
   int rc;
   if (c.p.scheme == CGKS_SCHEME_GKS2)
-    rc = f64 ? stage2<double, 1>(c, dt) : stage2<float, 1>(c, dt);
+    rc = f64 ? stage2<double, 1>(c, ctl) : stage2<float, 1>(c, ctl);
   else if (f64)
-    rc = stage5<double, 0>(c, c.at<double>(c.L.Q), c.at<double>(c.L.G), dt);
+    rc = stage5<double, 0>(c, c.at<double>(c.L.Q), c.at<double>(c.L.G), ctl);
   else
-    rc = stage5<float, 0>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G), dt);
+    rc = stage5<float, 0>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G), ctl);
   if (rc) return rc;
   const size_t N = c.g.N;
   if (L) HIPCK(hipMemcpyAsync(L, c.ws + c.L.Acc, 5 * N * 8, hipMemcpyDeviceToHost, c.stream));
@@ -621,13 +666,14 @@ int cgks_stage_sampled(void* ctx, double dt, const long* cells, long n, double* 
   const size_t ibytes = ((size_t)n * 4 + 255) & ~(size_t)255;
   if (ibytes + 40 * (size_t)n * 8 > fbytes) return CGKS_EINVAL;
   const bool f64 = c.p.precision == CGKS_PREC_FP64;
+  const double* ctl = set_dt(c, dt);
   int rc;
   if (!c5)
-    rc = f64 ? stage2<double, 1>(c, dt) : stage2<float, 1>(c, dt);
+    rc = f64 ? stage2<double, 1>(c, ctl) : stage2<float, 1>(c, ctl);
   else if (f64)
-    rc = stage5<double, 0>(c, c.at<double>(c.L.Q), c.at<double>(c.L.G), dt);
+    rc = stage5<double, 0>(c, c.at<double>(c.L.Q), c.at<double>(c.L.G), ctl);
   else
-    rc = stage5<float, 0>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G), dt);
+    rc = stage5<float, 0>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G), ctl);
   if (rc) return rc;
   std::vector<uint32_t> idx(cells, cells + n);
   uint32_t* didx = c.at<uint32_t>(c.L.F);

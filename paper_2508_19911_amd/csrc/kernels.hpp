@@ -275,8 +275,10 @@ struct FluxShared {
 template <class T, int DIR>
 __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 2 : 1) void k_flux5(Grid g, const double* __restrict__ Q,
                                                     const T* __restrict__ C, T* __restrict__ F,
-                                                    FluxParams fp, double dt) {
+                                                    FluxParams fp, const double* __restrict__ ctl) {
   __shared__ FluxShared<T> sh;
+  if (ctl[1] != 0.0) return;  // the step was stopped (see k_step_control)
+  const double dt = ctl[0];
   constexpr int FP = 2 * DIR + 1;  // tables of the + face of the axis
   using CB = CoefBlock<T>;
   using V = typename Vec16<T>::type;
@@ -399,9 +401,10 @@ struct Stage5Out {
 template <class T, int STAGE>  // 0 debug, 1 first stage, 2 second stage
 __global__ __launch_bounds__(BLK) void k_update5(Grid g, const T* __restrict__ F,
                                                  const double* __restrict__ Qn, Stage5Out o,
-                                                 double dt) {
+                                                 const double* __restrict__ ctl) {
   const int cell = blockIdx.x * BLK + threadIdx.x;
-  if (cell >= g.N) return;
+  if (cell >= g.N || ctl[1] != 0.0) return;
+  const double dt = ctl[0];
   int i, j, k;
   cell_ijk(g, cell, i, j, k);
   const long long N = g.N;
@@ -522,9 +525,10 @@ __global__ __launch_bounds__(BLK) void k_slopes2(Grid g, const double* __restric
 template <class T, int DIR>
 __global__ __launch_bounds__(BLK) void k_flux2(Grid g, const double* __restrict__ Q,
                                                const T* __restrict__ S, T* __restrict__ F,
-                                               FluxParams fp, double dt) {
+                                               FluxParams fp, const double* __restrict__ ctl) {
   const int cell = blockIdx.x * BLK + threadIdx.x;
-  if (cell >= g.N) return;
+  if (cell >= g.N || ctl[1] != 0.0) return;
+  const double dt = ctl[0];
   int i, j, k;
   cell_ijk(g, cell, i, j, k);
   const int left = neighbour_m<DIR>(g, cell, i, j, k);
@@ -557,9 +561,10 @@ __global__ __launch_bounds__(BLK) void k_flux2(Grid g, const double* __restrict_
 
 template <class T, int DEBUG>
 __global__ __launch_bounds__(BLK) void k_update2(Grid g, const T* __restrict__ F, double* Q,
-                                                 double* Lout, double* Ltout, double dt) {
+                                                 double* Lout, double* Ltout, const double* __restrict__ ctl) {
   const int cell = blockIdx.x * BLK + threadIdx.x;
-  if (cell >= g.N) return;
+  if (cell >= g.N || ctl[1] != 0.0) return;
+  const double dt = ctl[0];
   int i, j, k;
   cell_ijk(g, cell, i, j, k);
   const long long N = g.N;
@@ -664,6 +669,51 @@ struct DiagOp {
     return (q == 9 || q == 10) ? fmin(a, b) : a + b;
   }
 };
+
+// ============================================================================ step control on the device
+// ctl[0] = dt of the current step, ctl[1] = 0 go / 1 stopped at t_stop / 2 stopped non-physical,
+// ctl[2] = t, ctl[3] = steps done.  The stage kernels read dt from ctl and do nothing once ctl[1] is
+// set, so a batch of steps runs without the host reading dt back after every step, and a stopped
+// batch leaves the state of the step it stopped at.
+__global__ void k_ctl_init(double* ctl, double t) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl[0] = 0.0;
+    ctl[1] = 0.0;
+    ctl[2] = t;
+    ctl[3] = 0.0;
+  }
+}
+__global__ void k_ctl_set_dt(double* ctl, double dt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl[0] = dt;
+    ctl[1] = 0.0;
+  }
+}
+// lim = (min h/(|U|+c), max nu, non-physical flag) from k_dt_final; dt = CFL lim0, and
+// CFL h_min^2/(3 lim1) when viscous; the last step is shortened to end at t_stop (> 0)
+__global__ void k_step_control(const double* __restrict__ lim, double* ctl, double cfl, double hmin,
+                               int viscous, double t_stop) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || ctl[1] != 0.0) return;
+  const double t = ctl[2];
+  if (t_stop > 0.0 && t >= t_stop) {
+    ctl[1] = 1.0;
+    return;
+  }
+  if (lim[2] != 0.0) {
+    ctl[1] = 2.0;
+    return;
+  }
+  double dt = cfl * lim[0];
+  if (viscous) dt = fmin(dt, cfl * hmin * hmin / (3.0 * lim[1]));
+  if (t_stop > 0.0 && t + dt > t_stop) dt = t_stop - t;
+  ctl[0] = dt;
+}
+__global__ void k_step_advance(double* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && ctl[1] == 0.0) {
+    ctl[2] += ctl[0];
+    ctl[3] += 1.0;
+  }
+}
 
 // diagnostics partials: 0 ek, 1 es, 2 ed, 3..7 sum Q, 8 flagged, 9 rho min, 10 p min
 template <class T, int CENTRAL>

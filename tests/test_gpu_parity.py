@@ -253,6 +253,26 @@ def test_nonphysical_reported_and_state_kept():
     assert np.array_equal(s.get_state()[0], q)
 
 
+def test_step_batches_and_t_stop():
+    """cgks_step queues its steps in batches with dt and the t_stop shortening decided on the device:
+    a t_stop reached inside the second batch gives the oracle's step count, time and state; a further
+    call at t_stop takes no step."""
+    case, st = make_state("tgv8")
+    case = case.with_(recon=1)
+    o, s = pair(case, st)
+    dt0 = o.compute_dt(0.5)
+    t_stop = 10.5 * dt0  # about 11 steps: inside the second batch, the last one shortened
+    rc, done, t = o.step(10 ** 6, 0.5, t_stop=t_stop)
+    assert rc == 0 and 9 <= done <= 16
+    rc_g, done_g, t_g = s.step(10 ** 6, 0.5, t_stop=t_stop)
+    assert rc_g == 0 and done_g == done and abs(t_g - t) <= 1e-13 * t and abs(t_g - t_stop) <= 1e-13 * t_stop
+    qo = o.get_state()[0]
+    qg = s.get_state()[0]
+    assert scaled_err(qg, qo, scales(case, st[0])["Q"]) <= 1e-12 * done
+    rc_g, done_g, t_g2 = s.step(5, 0.5, t_stop=t_stop)
+    assert rc_g == 0 and done_g == 0 and t_g2 == t_g
+
+
 def test_conservation_fp32_bulk():
     case, st = make_state("ragged_viscous")
     case = case.with_(recon=1)
