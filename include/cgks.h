@@ -104,7 +104,8 @@ int cgks_get_state(void* ctx, double* q, double* g, double* t, long* step);
 int cgks_compute_dt(void* ctx, double cfl, double* dt);
 /* Advance nsteps steps at CFL number cfl; when t_stop > 0 the last step is shortened to end at
  * t_stop and stepping stops there.  *steps_done / *t_now report progress (also on error).
- * ENONPHYSICAL leaves the state as it was at the start of the failing step. */
+ * ENONPHYSICAL leaves the state as it was at the start of the failing step.  dt and the stop are
+ * decided on the device; steps are queued in batches and the host waits once per batch. */
 int cgks_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done, double* t_now);
 /* Advance nsteps steps of the given dt (no CFL evaluation). */
 int cgks_step_fixed(void* ctx, int nsteps, double dt);
