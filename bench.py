@@ -38,8 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # write), from two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE) scaled by a 1 GiB copy
 # kernel: profiles/flux_tgv128_hbm_counters.md.  Valid only for the kernel sources they were taken
 # on; any change to those sources makes the reported traffic null until the counters are retaken.
-FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8763e+09,
-                "sources_sha256": "8c2369ed6f773f3b5a7b93063a3537c8664f6279d1a690ae88b457d2d32d299d"}
+FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8718e+09,
+                "sources_sha256": "145bd589d0043846f98009ffd92fb7c2d36f1f059c819512a1f433bfb81c14b6"}
 KERNEL_SOURCES = ["common.hpp", "gks_flux.hpp", "recon.hpp", "recon_tables.hpp", "kernels.hpp"]
 
 
