@@ -71,6 +71,20 @@ def run(cgks, case, precision, t_end, dt_out, label, indicator=None, quad=True):
             "epsD_peak": float(h[:, 3].max()), "history": keep_hist}
 
 
+def flow_cases(flow):
+    """(CGKS-5th case, GKS-2nd case, the paper's table) of one comparison (Sec. 4.1 or 4.2)."""
+    from . import cgks, inputs
+    if flow == "subsonic":
+        c5 = inputs.tgv_case(96).with_(recon=cgks.RECON_LINEAR)
+        c2 = inputs.tgv_case(296).with_(scheme=cgks.SCHEME_GKS2, recon=cgks.RECON_LINEAR)
+        paper = {"cgks5_seconds": 876, "gks2_seconds": 7746, "ratio": 8.8, "hardware": "2x RTX 4090, FP64"}
+    else:
+        c5 = inputs.tgv_case(116, ma=2.0, supersonic=True).with_(recon=cgks.RECON_NONLINEAR)
+        c2 = inputs.tgv_case(384, ma=2.0, supersonic=True).with_(scheme=cgks.SCHEME_GKS2, recon=cgks.RECON_NONLINEAR)
+        paper = {"cgks5_seconds": 407, "gks2_seconds": 2842, "ratio": 7.0, "hardware": "4x RTX 4090, FP64"}
+    return c5, c2, paper
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--flow", choices=["subsonic", "supersonic"], default="subsonic")
@@ -86,14 +100,7 @@ def main():
     from . import cgks, inputs
 
     cgks.load()
-    if args.flow == "subsonic":
-        c5 = inputs.tgv_case(96).with_(recon=cgks.RECON_LINEAR)
-        c2 = inputs.tgv_case(296).with_(scheme=cgks.SCHEME_GKS2, recon=cgks.RECON_LINEAR)
-        paper = {"cgks5_seconds": 876, "gks2_seconds": 7746, "ratio": 8.8, "hardware": "2x RTX 4090, FP64"}
-    else:
-        c5 = inputs.tgv_case(116, ma=2.0, supersonic=True).with_(recon=cgks.RECON_NONLINEAR)
-        c2 = inputs.tgv_case(384, ma=2.0, supersonic=True).with_(scheme=cgks.SCHEME_GKS2, recon=cgks.RECON_NONLINEAR)
-        paper = {"cgks5_seconds": 407, "gks2_seconds": 2842, "ratio": 7.0, "hardware": "4x RTX 4090, FP64"}
+    c5, c2, paper = flow_cases(args.flow)
     quad = not args.one_point
     out = {"flow": args.flow, "t_end": args.t_end, "cfl": c5.cfl, "paper_table": paper,
            "diagnostics": "quadrature" if quad else "one-point", "runs": {}}

@@ -79,10 +79,16 @@ def vortex_case(n: int = 64, **kw) -> Case:
     return c.with_(**kw) if kw else c
 
 
-def tgv_case(n: int = 128, ma: float = 0.1, re: float = 1600.0, prandtl: float = 0.72,
+def tgv_case(n: int = 128, ma: float = 0.1, re: float = 1600.0, prandtl: float | None = None,
              supersonic: bool = False, **kw) -> Case:
-    """Taylor-Green vortex, periodic [0, 2pi]^3; mu0 = rho0 U0 L / Re, Sutherland with T_ref = p0/rho0."""
+    """Taylor-Green vortex, periodic [0, 2pi]^3; mu0 = rho0 U0 L / Re, Sutherland with T_ref = p0/rho0.
+
+    Subsonic (Sec. 4.1): rho0 = U0 = 1, p0 from the Mach number.  Supersonic (Sec. 4.2): rho0 = p0 = 1,
+    U0 = sqrt(gamma) Ma.  The Prandtl number defaults to the supersonic section's 0.7; Sec. 4.1 states
+    none, and the subsonic flow takes air's 0.72."""
     gamma = 1.4
+    if prandtl is None:
+        prandtl = 0.7 if supersonic else 0.72
     if supersonic:
         rho0, p0, u0 = 1.0, 1.0, math.sqrt(gamma) * ma
     else:
