@@ -16,8 +16,10 @@ Metric: Mcell-stage updates/s = cells x 2 stages x K / timed seconds, for
     the flagged fraction of the learned run.
 The roofline object is for the face-flux kernel (the dominant one): algorithmic flops per launch
 (flops.json, counted from the kernel's own templates) over its mean launch time, taken with HIP events
-on the library's stream during the timed region.  cpu_baseline times the FP64 oracle on host cores
-over a bounded sample of the same flow.
+on the library's stream during the timed region (only the flux launches carry events there).
+kernels_ms is a per-class breakdown from as many further steps after the timed region, with every
+launch between events.  cpu_baseline times the FP64 oracle on host cores over a bounded sample of
+the same flow.
 """
 from __future__ import annotations
 
@@ -38,8 +40,8 @@ HBM_PEAK_GBS = 8000.0
 # write), from two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE) scaled by a 1 GiB copy
 # kernel: profiles/flux_tgv128_hbm_counters.md.  Valid only for the kernel sources they were taken
 # on; any change to those sources makes the reported traffic null until the counters are retaken.
-FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8718e+09,
-                "sources_sha256": "145bd589d0043846f98009ffd92fb7c2d36f1f059c819512a1f433bfb81c14b6"}
+FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8720e+09,
+                "sources_sha256": "d03c1a8dda43c11b67dfbb9aaba0f6e04e677a4c655b3297b1f5eedd7c9f727c"}
 KERNEL_SOURCES = ["common.hpp", "gks_flux.hpp", "recon.hpp", "recon_tables.hpp", "kernels.hpp"]
 
 
@@ -66,7 +68,10 @@ def load_indicator():
     return z["params"].astype("float32"), float(z["logit_threshold"])
 
 
-def run_variant(case, precision, steps, warmup, timing, indicator=None):
+def run_variant(case, precision, steps, warmup, timing, indicator=None, breakdown_steps=0):
+    """Time `steps` steps after `warmup`.  timing: True brackets the face-flux launches of the timed
+    steps with HIP events (the other kernels run without events between them); breakdown_steps > 0
+    then runs that many more steps, after the timed region, with every kernel class timed."""
     import numpy as np
     import torch
     from paper_2508_19911_amd import cgks
@@ -79,21 +84,28 @@ def run_variant(case, precision, steps, warmup, timing, indicator=None):
     s.step(warmup, case.cfl)
     torch.cuda.synchronize()
     if timing:
-        s.timing(True)
+        s.timing(True, classes=["flux"])
         s.timing_read()
     t0 = time.perf_counter()
     _, done, t_now = s.step(steps, case.cfl)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = s.timing_read() if timing else None
-    s.timing(False)
     diag = s.diagnostics(case.rho0, case.u0)
     q, _, _, _ = s.get_state()
     vel = q[1:4] / q[0]
+    breakdown = None
+    if breakdown_steps:
+        s.timing(True)
+        s.timing_read()
+        s.step(breakdown_steps, case.cfl)
+        breakdown = s.timing_read()
+    s.timing(False)
     s.close()
     del s
     torch.cuda.empty_cache()
-    return {"seconds": t1 - t0, "steps": done, "t": t_now, "kernels": kt, "diag": diag, "vel": vel}
+    return {"seconds": t1 - t0, "steps": done, "t": t_now, "kernels": kt, "diag": diag, "vel": vel,
+            "breakdown": breakdown, "breakdown_steps": breakdown_steps}
 
 
 def copy_calibration(nbytes=1 << 30):
@@ -157,14 +169,15 @@ def main():
     N = base.N
 
     head_case = base.with_(recon=cgks.RECON_LEARNED if indicator is not None else cgks.RECON_NONLINEAR)
-    head = run_variant(head_case, cgks.PREC_FP32_BULK, args.steps, args.warmup, True, indicator)
+    head = run_variant(head_case, cgks.PREC_FP32_BULK, args.steps, args.warmup, True, indicator,
+                       breakdown_steps=args.steps)
     rate = N * 2 * head["steps"] / head["seconds"] / 1e6
 
     # context: FP32-bulk with GENO everywhere (the same form without the learned switch)
     geno32 = None
     if indicator is not None and not args.no_fp64:
         geno32 = run_variant(base.with_(recon=cgks.RECON_NONLINEAR), cgks.PREC_FP32_BULK, args.steps,
-                             args.warmup, False)
+                             args.warmup, True)
 
     fp64 = None
     if not args.no_fp64:
@@ -180,7 +193,9 @@ def main():
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": traffic, "kernel": "k_flux5<float>",
             "flops_per_launch": per_cell * N, "mean_launch_ms": round(flux_ms, 4)}
-    kernels = {k: {"launches": c, "ms": round(m, 3)} for k, (c, m) in head["kernels"].items()}
+    # per-class breakdown from the steps after the timed region, every launch between events
+    kernels = {k: {"launches": c, "ms": round(m, 3)} for k, (c, m) in head["breakdown"].items()}
+    kernels["steps"] = head["breakdown_steps"]
 
     line = {
         "metric": "Mcell-stage updates/s at 1 GPU, FP32+learned vs FP64 plain, at equal L2 error",

@@ -161,13 +161,18 @@ int cgks_indicator_grad(void* ctx, const void* dev_x, const void* dev_y, long n,
                         double* grad);
 
 /* ---- kernel timing ---------------------------------------------------------------------------------
- * When enabled, every kernel launch of the sweep is bracketed by HIP events on the context's stream.
- * cgks_timing_read synchronises the stream and returns, per kernel class, the number of launches and
- * their summed duration in ms since the previous read (then resets).  Classes (CGKS_KC_*): 0 time-step
- * reduction, 1 indicator inference, 2 reconstruction coefficients, 3 face flux, 4 stage update. */
+ * When enabled, the sweep's kernel launches of the selected classes are bracketed by HIP events on the
+ * context's stream.  cgks_timing_read synchronises the stream and returns, per kernel class, the number
+ * of launches and their summed duration in ms since the previous read (then resets).  Classes
+ * (CGKS_KC_*): 0 time-step reduction, 1 indicator inference, 2 reconstruction coefficients, 3 face
+ * flux, 4 stage update.
+ * cgks_timing_enable: classes = 0 stops timing; 1 (or any negative value) times every class; otherwise
+ * classes = 2 * (bit mask of the timed classes, bit k = class k), e.g. 2 << CGKS_KC_FLUX for the face
+ * flux alone.  Enabling creates the events a few hundred launches need up front, so that timed steps
+ * create none.  Returns CGKS_EINVAL for a NULL context, CGKS_EDEVICE if an event cannot be created. */
 enum { CGKS_KC_DT = 0, CGKS_KC_INFER = 1, CGKS_KC_COEF = 2, CGKS_KC_FLUX = 3, CGKS_KC_UPDATE = 4,
        CGKS_KC_COUNT = 5 };
-int cgks_timing_enable(void* ctx, int on);
+int cgks_timing_enable(void* ctx, int classes);
 int cgks_timing_read(void* ctx, long* count, double* ms, int nclasses);
 
 /* ---- unit-parity hooks (the hot path's device routines on host-supplied inputs) ----------------------

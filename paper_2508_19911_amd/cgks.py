@@ -252,8 +252,12 @@ class Solver:
             float(lr), int(seed), ctypes.byref(loss)))
         return loss.value
 
-    def timing(self, on=True):
-        _check("cgks_timing_enable", load().cgks_timing_enable(self.h, int(on)))
+    def timing(self, on=True, classes=None):
+        """Time the sweep's launches with HIP events: every class, or only `classes` (names from
+        KERNEL_CLASSES); on=False stops."""
+        code = 0 if not on else (1 if classes is None else
+                                 2 * sum(1 << KERNEL_CLASSES.index(k) for k in set(classes)))
+        _check("cgks_timing_enable", load().cgks_timing_enable(self.h, code))
 
     def timing_read(self):
         """{class: (launches, summed ms)} since the previous read."""

@@ -75,6 +75,7 @@ Layout layout(const cgks_params* p) {
 
 struct Timing {
   bool on = false;
+  unsigned mask = 0;  // bit k: class k is timed
   struct Rec {
     int cls;
     hipEvent_t a, b;
@@ -95,6 +96,7 @@ struct Ctx {
   double vk_eps2;
   double t = 0.0;
   long step = 0;
+  double dt_hint = 0.0;  // the last CFL time step read back (sizes the batches before a t_stop)
   bool have_state = false;
   bool have_mlp = false;
   int nblk;
@@ -141,7 +143,8 @@ struct TimedScope {
   hipEvent_t a = nullptr;
   // a record that fails drops this measurement (timing is diagnostic; the launches are unaffected)
   TimedScope(Ctx& ctx, int k) : c(ctx), cls(k) {
-    if (c.tm.on && (a = timing_event(c)) && hipEventRecord(a, c.stream) != hipSuccess) {
+    if (c.tm.on && ((c.tm.mask >> k) & 1u) && (a = timing_event(c)) &&
+        hipEventRecord(a, c.stream) != hipSuccess) {
       c.tm.pool.push_back(a);
       a = nullptr;
     }
@@ -160,23 +163,24 @@ struct TimedScope {
 
 // ---------------------------------------------------------------------------- stage sequences
 template <class T>
-int run_flags(Ctx& c, const double* Q, const T* G) {
+int run_flags(Ctx& c, const double* Q, const T* G, const double* ctl = nullptr) {
   if (c.p.recon != CGKS_RECON_LEARNED) return CGKS_OK;
   TimedScope ts(c, CGKS_KC_INFER);
   return mlp::launch_infer<T>(c.g, Q, G, c.at<float>(c.L.mlp), c.at<unsigned char>(c.L.flags),
-                              nullptr, c.p.indicator_logit, c.at<char>(c.L.mlp), c.stream);
+                              nullptr, c.p.indicator_logit, c.at<char>(c.L.mlp), c.stream, ctl);
 }
 
+// ctl: the step control; a stopped step skips the launch (nullptr: always run)
 template <class T>
-int launch_coef(Ctx& c, const double* Q, const T* G) {
+int launch_coef(Ctx& c, const double* Q, const T* G, const double* ctl = nullptr) {
   const dim3 grid(coef_blocks(c.g), 5), blk(BLK);  // y: the conservative variable
   T* C = c.at<T>(c.L.C);
   const unsigned char* fl = c.at<unsigned char>(c.L.flags);
   TimedScope ts(c, CGKS_KC_COEF);
   switch (c.p.recon) {
-    case CGKS_RECON_LINEAR: k_coef<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp); break;
-    case CGKS_RECON_NONLINEAR: k_coef<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp); break;
-    default: k_coef<T, 2><<<grid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp); break;
+    case CGKS_RECON_LINEAR: k_coef<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp, ctl); break;
+    case CGKS_RECON_NONLINEAR: k_coef<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp, ctl); break;
+    default: k_coef<T, 2><<<grid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp, ctl); break;
   }
   LAUNCHCK("k_coef");
   return CGKS_OK;
@@ -186,9 +190,9 @@ int launch_coef(Ctx& c, const double* Q, const T* G) {
 // per time step, on the first stage's input; the second stage keeps its flags.
 template <class T, int STAGE>
 int stage5(Ctx& c, const double* Q, const T* G, const double* ctl) {
-  int rc = STAGE == 2 ? CGKS_OK : run_flags<T>(c, Q, G);
+  int rc = STAGE == 2 ? CGKS_OK : run_flags<T>(c, Q, G, ctl);
   if (rc) return rc;
-  rc = launch_coef<T>(c, Q, G);
+  rc = launch_coef<T>(c, Q, G, ctl);
   if (rc) return rc;
   const dim3 grid(c.nblk), blk(BLK);
   const dim3 fgrid((unsigned)((c.g.N + FLUX_FACES - 1) / FLUX_FACES)), fblk(FLUX_BLK);
@@ -231,9 +235,9 @@ int stage2(Ctx& c, const double* ctl) {
   {
     TimedScope ts(c, CGKS_KC_COEF);
     if (c.p.recon == CGKS_RECON_NONLINEAR)
-      k_slopes2<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, S, c.vk_eps2);
+      k_slopes2<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, S, c.vk_eps2, ctl);
     else
-      k_slopes2<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, S, c.vk_eps2);
+      k_slopes2<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, S, c.vk_eps2, ctl);
   }
   {
     TimedScope t0(c, CGKS_KC_FLUX);
@@ -323,15 +327,15 @@ int diag_quad(Ctx& c, double* r) {
     const unsigned char* fl = c.at<unsigned char>(c.L.flags);
     const dim3 cgrid(coef_blocks(c.g), 5);
     if (c.p.recon == CGKS_RECON_LINEAR)
-      k_coef<T, 0><<<cgrid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp);
+      k_coef<T, 0><<<cgrid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp, nullptr);
     else  // GENO everywhere (also for the learned form)
-      k_coef<T, 1><<<cgrid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp);
+      k_coef<T, 1><<<cgrid, blk, 0, c.stream>>>(c.g, Q, G, fl, C, c.gp, nullptr);
     k_diag_quad5<T><<<grid, blk, 0, c.stream>>>(c.g, Q, C, c.fp, part);
   } else {
     if (c.p.recon == CGKS_RECON_NONLINEAR)
-      k_slopes2<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, C, c.vk_eps2);
+      k_slopes2<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, C, c.vk_eps2, nullptr);
     else
-      k_slopes2<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, C, c.vk_eps2);
+      k_slopes2<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, C, c.vk_eps2, nullptr);
     k_diag_quad2<T><<<grid, blk, 0, c.stream>>>(c.g, Q, C, c.fp, part);
   }
   k_diag_final<<<1, BLK, 0, c.stream>>>(c.nblk, part, scal);
@@ -401,10 +405,18 @@ int cgks_destroy(void* ctx) {
   return sync == hipSuccess ? CGKS_OK : dev_error("hipStreamSynchronize", sync);
 }
 
-int cgks_timing_enable(void* ctx, int on) {
+int cgks_timing_enable(void* ctx, int classes) {
   if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
-  c.tm.on = on != 0;
+  c.tm.on = classes != 0;
+  c.tm.mask = (classes == 1 || classes < 0) ? ~0u : (unsigned)classes >> 1;
+  // events for 256 timed launches, created now rather than between timed launches
+  constexpr size_t POOL = 512;
+  while (c.tm.on && c.tm.pool.size() + 2 * c.tm.recs.size() < POOL) {
+    hipEvent_t e;
+    HIPCK(hipEventCreate(&e));
+    c.tm.pool.push_back(e);
+  }
   return CGKS_OK;
 }
 
@@ -457,6 +469,7 @@ int cgks_set_state(void* ctx, const double* q, const double* g, double t, long s
   HIPCK(hipStreamSynchronize(c.stream));
   c.t = t;
   c.step = step;
+  c.dt_hint = 0.0;
   c.have_state = true;
   return CGKS_OK;
 }
@@ -489,6 +502,7 @@ int cgks_set_ic(void* ctx, int kind, const double* prm, int nprm) {
   HIPCK(hipStreamSynchronize(c.stream));
   c.t = 0.0;
   c.step = 0;
+  c.dt_hint = 0.0;
   c.have_state = true;
   return CGKS_OK;
 }
@@ -547,9 +561,15 @@ int cgks_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done,
     const double t0 = c.t;
     k_ctl_init<<<1, 64, 0, c.stream>>>(ctl, t0);
     int queued = 0;
-    double h[4] = {0.0, 0.0, t0, 0.0};
+    double h[5] = {0.0, 0.0, t0, 0.0, c.dt_hint};
     while (rc == CGKS_OK && queued < nsteps) {
-      const int batch = std::min(STEP_BATCH, nsteps - queued);
+      int batch = std::min(STEP_BATCH, nsteps - queued);
+      // before a t_stop, queue the steps the last time step says are left and one more: dt drifts
+      // slowly, an underestimate costs one more batch, and steps queued past t_stop do no work
+      if (t_stop > 0.0 && h[4] > 0.0) {
+        const double left = (t_stop - h[2]) / h[4];
+        if (left < batch - 1) batch = std::max(1, (int)std::ceil(left) + 1);
+      }
       for (int b = 0; b < batch && rc == CGKS_OK; ++b) {
         {
           TimedScope ts(c, CGKS_KC_DT);
@@ -567,7 +587,7 @@ int cgks_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done,
       queued += batch;
       if (rc != CGKS_OK) break;
       {
-        hipError_t e = hipMemcpyAsync(h, ctl, 4 * sizeof(double), hipMemcpyDeviceToHost, c.stream);
+        hipError_t e = hipMemcpyAsync(h, ctl, 5 * sizeof(double), hipMemcpyDeviceToHost, c.stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
         if (e != hipSuccess) {
           rc = dev_error("step control read-back", e);
@@ -580,6 +600,7 @@ int cgks_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done,
     done = (int)h[3];
     c.t = h[2];
     c.step += done;
+    if (h[4] > 0.0) c.dt_hint = h[4];
   }
   if (rc == CGKS_OK) {
     hipError_t e = hipStreamSynchronize(c.stream);

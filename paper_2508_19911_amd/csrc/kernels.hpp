@@ -190,8 +190,10 @@ template <class T, int MODE>  // MODE 0 linear, 1 GENO everywhere, 2 GENO where 
 __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__ Q,
                                               const T* __restrict__ G,
                                               const unsigned char* __restrict__ flags,
-                                              T* __restrict__ C, GenoParams gp) {
+                                              T* __restrict__ C, GenoParams gp,
+                                              const double* __restrict__ ctl) {
   __shared__ CoefShared<T> sh;
+  if (ctl && ctl[1] != 0.0) return;  // the step was stopped (see k_step_control)
   const int v = blockIdx.y;
   const int nbx = (g.nx + COEF_TX - 1) / COEF_TX, nby = (g.ny + COEF_TY - 1) / COEF_TY;
   // contiguous tile ranges per XCD: the halo rows a tile shares with its y and z neighbours (2 and
@@ -474,9 +476,10 @@ __global__ __launch_bounds__(BLK) void k_update5(Grid g, const T* __restrict__ F
 // ============================================================================ GKS-2nd
 template <class T, int LIM>
 __global__ __launch_bounds__(BLK) void k_slopes2(Grid g, const double* __restrict__ Q,
-                                                 T* __restrict__ S, double vk_eps2) {
+                                                 T* __restrict__ S, double vk_eps2,
+                                                 const double* __restrict__ ctl) {
   const int cell = blockIdx.x * BLK + threadIdx.x;
-  if (cell >= g.N) return;
+  if (cell >= g.N || (ctl && ctl[1] != 0.0)) return;  // ctl: a stopped step skips the slopes
   int i, j, k;
   cell_ijk(g, cell, i, j, k);
   const long long N = g.N;
@@ -681,6 +684,7 @@ __global__ void k_ctl_init(double* ctl, double t) {
     ctl[1] = 0.0;
     ctl[2] = t;
     ctl[3] = 0.0;
+    ctl[4] = 0.0;
   }
 }
 __global__ void k_ctl_set_dt(double* ctl, double dt) {
@@ -690,7 +694,8 @@ __global__ void k_ctl_set_dt(double* ctl, double dt) {
   }
 }
 // lim = (min h/(|U|+c), max nu, non-physical flag) from k_dt_final; dt = CFL lim0, and
-// CFL h_min^2/(3 lim1) when viscous; the last step is shortened to end at t_stop (> 0)
+// CFL h_min^2/(3 lim1) when viscous; the last step is shortened to end at t_stop (> 0).
+// ctl = (dt, stop: 1 at t_stop, 2 non-physical, t, steps taken, dt before the shortening)
 __global__ void k_step_control(const double* __restrict__ lim, double* ctl, double cfl, double hmin,
                                int viscous, double t_stop) {
   if (threadIdx.x != 0 || blockIdx.x != 0 || ctl[1] != 0.0) return;
@@ -705,6 +710,7 @@ __global__ void k_step_control(const double* __restrict__ lim, double* ctl, doub
   }
   double dt = cfl * lim[0];
   if (viscous) dt = fmin(dt, cfl * hmin * hmin / (3.0 * lim[1]));
+  ctl[4] = dt;
   if (t_stop > 0.0 && t + dt > t_stop) dt = t_stop - t;
   ctl[0] = dt;
 }

@@ -293,7 +293,9 @@ __global__ __launch_bounds__(256) void k_infer(Grid g, const double* __restrict_
                                                const T* __restrict__ G,
                                                const float* __restrict__ params,
                                                unsigned char* __restrict__ flags,
-                                               float* __restrict__ logits, float thr) {
+                                               float* __restrict__ logits, float thr,
+                                               const double* __restrict__ ctl) {
+  if (ctl && ctl[1] != 0.0) return;  // the step was stopped (see k_step_control)
   __shared__ WaveLDS wl[4];
   // bf16 weights, rows padded like the activations: W1 [32][XS], W2 and W3 [32][HS]
   constexpr int OWS2 = 32 * XS, OWS3 = OWS2 + 32 * HS, NWS = OWS3 + 32 * HS;
@@ -351,8 +353,9 @@ __global__ __launch_bounds__(256) void k_infer(Grid g, const double* __restrict_
 
 template <class T>
 int launch_infer(const Grid& g, const double* Q, const T* G, const float* params,
-                 unsigned char* flags, float* logits, double thr, char* /*ws*/, hipStream_t s) {
-  k_infer<T><<<(unsigned)((g.N + 255) / 256), 256, 0, s>>>(g, Q, G, params, flags, logits, (float)thr);
+                 unsigned char* flags, float* logits, double thr, char* /*ws*/, hipStream_t s,
+                 const double* ctl = nullptr) {
+  k_infer<T><<<(unsigned)((g.N + 255) / 256), 256, 0, s>>>(g, Q, G, params, flags, logits, (float)thr, ctl);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

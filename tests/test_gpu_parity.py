@@ -273,6 +273,59 @@ def test_step_batches_and_t_stop():
     assert rc_g == 0 and done_g == 0 and t_g2 == t_g
 
 
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_repeated_t_stop_calls(scheme):
+    """Output-interval loop: successive calls each run to the next t_stop (a few steps each, the
+    batches then sized from the last time step).  Step counts, times and the state follow the oracle
+    making the same calls."""
+    case, st = make_state("tgv8")
+    case = case.with_(scheme=scheme, recon=1)
+    o, s = pair(case, st)
+    dt0 = o.compute_dt(0.5)
+    total = 0
+    for k in range(1, 6):
+        t_stop = 2.7 * k * dt0
+        rc, done, t = o.step(10 ** 6, 0.5, t_stop=t_stop)
+        rc_g, done_g, t_g = s.step(10 ** 6, 0.5, t_stop=t_stop)
+        assert rc == rc_g == 0 and done_g == done and abs(t_g - t) <= 1e-13 * t, (k, done, done_g, t, t_g)
+        total += done
+    assert total >= 13
+    assert scaled_err(s.get_state()[0], o.get_state()[0], scales(case, st[0])["Q"]) <= 1e-12 * total
+
+
+@pytest.mark.parametrize("recon", [1, 2])
+def test_kernel_timing_classes(recon):
+    """Timing every class counts each step's launches (one time-step reduction, per stage one
+    coefficient launch, three face-flux launches and one update; the indicator once per step); timing
+    the face flux alone records only its launches; timed steps give the untimed state bitwise."""
+    cgks = cg()
+    case = inputs.tgv_case(12, ma=0.3).with_(recon=recon)
+    st = inputs.tgv_state(case)
+    states = []
+    for classes in (None, ["flux"], "off"):
+        s = cgks.Solver(case, precision=1)
+        if recon == 2:
+            s.indicator_set(np.zeros(cgks.MLP_NPARAM, dtype=np.float32), 0.0)
+        s.set_state(*st)
+        if classes != "off":
+            s.timing(True, classes=classes)
+        _, done, _ = s.step(3, 0.5)
+        assert done == 3
+        kt = s.timing_read()
+        if classes is None:
+            assert kt["dt"][0] == 3 and kt["coef"][0] == 6 and kt["flux"][0] == 18 and kt["update"][0] == 6
+            assert kt["infer"][0] == (3 if recon == 2 else 0)
+            assert all(ms > 0.0 for c, ms in kt.values() if c)
+        elif classes == ["flux"]:
+            assert kt["flux"][0] == 18 and kt["flux"][1] > 0.0
+            assert all(kt[k] == (0, 0.0) for k in ("dt", "infer", "coef", "update"))
+        else:
+            assert all(v == (0, 0.0) for v in kt.values())
+        states.append(s.get_state()[0])
+        s.close()
+    assert np.array_equal(states[0], states[2]) and np.array_equal(states[1], states[2])
+
+
 def test_conservation_fp32_bulk():
     case, st = make_state("ragged_viscous")
     case = case.with_(recon=1)

@@ -114,6 +114,7 @@ def test_null_context_is_rejected_without_device_work():
     assert lib.cgks_set_ic(z, 1, None, 0) == -1
     assert lib.cgks_get_flags(z, None) == -1
     assert lib.cgks_diagnostics_quad(z, 1.0, 1.0, None) == -1
+    assert lib.cgks_timing_enable(z, 1) == -1
     assert lib.cgks_destroy(z) == 0  # destroying nothing is a no-op
 
 
