@@ -193,6 +193,10 @@ def main():
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": traffic, "kernel": "k_flux5<float>",
             "flops_per_launch": per_cell * N, "mean_launch_ms": round(flux_ms, 4)}
+    if traffic is not None:  # the same launch against the HBM roof: measured bytes over its mean time
+        gbs = traffic / (flux_ms * 1e-3) / 1e9
+        roof["hbm_achieved_gbs"] = round(gbs, 1)
+        roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
     # per-class breakdown from the steps after the timed region, every launch between events
     kernels = {k: {"launches": c, "ms": round(m, 3)} for k, (c, m) in head["breakdown"].items()}
     kernels["steps"] = head["breakdown_steps"]
