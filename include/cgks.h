@@ -105,7 +105,9 @@ int cgks_compute_dt(void* ctx, double cfl, double* dt);
 /* Advance nsteps steps at CFL number cfl; when t_stop > 0 the last step is shortened to end at
  * t_stop and stepping stops there.  *steps_done / *t_now report progress (also on error).
  * ENONPHYSICAL leaves the state as it was at the start of the failing step.  dt and the stop are
- * decided on the device; steps are queued in batches and the host waits once per batch. */
+ * decided on the device; steps are queued in batches (at most 8; before a t_stop, as many as the
+ * last time step says are left, plus one) and the host waits once per batch.  A step queued after
+ * the stop launches its kernels, which return at once. */
 int cgks_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done, double* t_now);
 /* Advance nsteps steps of the given dt (no CFL evaluation). */
 int cgks_step_fixed(void* ctx, int nsteps, double dt);
