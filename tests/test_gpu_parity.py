@@ -273,6 +273,30 @@ def test_step_batches_and_t_stop():
     assert rc_g == 0 and done_g == 0 and t_g2 == t_g
 
 
+@pytest.mark.parametrize("nsteps", [1, 8, 9, 17])
+def test_batched_steps_equal_single_steps(nsteps):
+    """nsteps steps in one call (queued in batches of up to 8) leave the same state, time and step
+    count, bit for bit, as nsteps calls of one step; a call of zero steps changes nothing."""
+    case, st = make_state("tgv8")
+    case = case.with_(recon=1)
+    a = cg().Solver(case, precision=1)
+    b = cg().Solver(case, precision=1)
+    a.set_state(*st)
+    b.set_state(*st)
+    rc, done, t = a.step(nsteps, 0.5)
+    assert rc == 0 and done == nsteps
+    for _ in range(nsteps):
+        assert b.step(1, 0.5)[1] == 1
+    qa, ga, ta, na = a.get_state()
+    qb, gb, tb, nb = b.get_state()
+    assert ta == tb == t and na == nb == nsteps
+    assert np.array_equal(qa, qb) and np.array_equal(ga, gb)
+    rc, done, t0 = a.step(0, 0.5)
+    assert rc == 0 and done == 0 and t0 == ta and np.array_equal(a.get_state()[0], qa)
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_repeated_t_stop_calls(scheme):
     """Output-interval loop: successive calls each run to the next t_stop (a few steps each, the
