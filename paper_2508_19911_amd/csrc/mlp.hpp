@@ -45,12 +45,8 @@ constexpr size_t OFF_GACC = OFF_LOSS + 4096;
 constexpr size_t OFF_END = OFF_GACC + 4352 * 8;
 inline size_t workspace_bytes() { return (OFF_END + 255) & ~size_t(255); }
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// float -> bf16 bits, round to nearest even: one hardware conversion on gfx950 (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(f)); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // ---------------------------------------------------------------------------- features
