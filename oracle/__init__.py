@@ -65,6 +65,7 @@ def lib():
         L.cgkso_stencil_offsets.argtypes = [P]
         L.cgkso_recon_cell.argtypes = [ctypes.POINTER(Params), P, P, P, D, I, P, P]
         L.cgkso_face_gauss_points.argtypes = [P]
+        L.cgkso_recon_cell_gks2.argtypes = [ctypes.POINTER(Params), P, P, I, P, P]
         L.cgkso_chi_deviation.argtypes = [ctypes.c_void_p, P]
         L.cgkso_stage_cells.argtypes = [ctypes.c_void_p, D, P, ctypes.c_long, P, P, P, P]
         L.cgkso_geno_scale.argtypes = [P, I]
@@ -269,6 +270,15 @@ def recon_cell(params: Params, q, g, h, mode, scale=1.0):
     lib().cgkso_recon_cell(ctypes.byref(params), _ptr(q), _ptr(g), _ptr(h), float(scale), int(mode),
                            _ptr(out), _ptr(info))
     return out, info
+
+
+def recon_cell_gks2(params: Params, q7, h, limited):
+    """GKS-2nd P^1 of one variable: q7 = (cell, -x, +x, -y, +y, -z, +z) averages.  Returns
+    out[6][4] (face-midpoint value and the three derivatives per face) and the limiter factor."""
+    q7 = np.ascontiguousarray(q7, dtype=np.float64); h = np.ascontiguousarray(h, dtype=np.float64)
+    out = np.zeros((6, 4)); phi = np.zeros(1)
+    lib().cgkso_recon_cell_gks2(ctypes.byref(params), _ptr(q7), _ptr(h), int(limited), _ptr(out), _ptr(phi))
+    return out, float(phi[0])
 
 
 def geno_scale(q5, v):

@@ -101,6 +101,13 @@ void cgkso_stencil_offsets(int* offsets);
  * mode 0 linear, 1 GENO. */
 void cgkso_recon_cell(const cgkso_params* p, const double* q, const double* g, const double* h,
                       double scale, int mode, double* out, double* info);
+/* GKS-2nd P^1 of one cell and one variable (Sec. 3.3): q7[7] = the cell average, then the averages
+ * of the neighbours at -x, +x, -y, +y, -z, +z; h[3] cell sizes; limited != 0 applies the
+ * Venkatakrishnan factor (reading R13: eps^2 = (K h)^3 with h the geometric mean cell size, phi the
+ * minimum over the six face midpoints).  out[6][4]: faces (-x,+x,-y,+y,-z,+z) x (value at the face
+ * midpoint, d/dx, d/dy, d/dz); *phi (may be NULL) receives the limiter factor. */
+void cgkso_recon_cell_gks2(const cgkso_params* p, const double* q7, const double* h, int limited,
+                           double* out, double* phi);
 /* Gauss point tangential offsets on a face (normalised units), gp[4][2]. */
 void cgkso_face_gauss_points(double* gp);
 /* The GENO scale of variable v (0..4) of the conservative cell average q5[5], the "scale" argument

@@ -372,4 +372,12 @@ void cgkso_face_gauss_points(double* gp) { face_gauss_points(reinterpret_cast<do
 
 double cgkso_geno_scale(const double* q5, int v) { return geno_scale(q5, v); }
 
+void cgkso_recon_cell_gks2(const cgkso_params* p, const double* q7, const double* h, int limited,
+                           double* out, double* phi) {
+  double b[3], ph;
+  gks2_slopes(*p, q7, h, limited, b, &ph);
+  recon_cell_gks2(*p, q7, h, limited, reinterpret_cast<double(*)[4]>(out));
+  if (phi) *phi = ph;
+}
+
 }  // extern "C"

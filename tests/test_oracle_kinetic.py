@@ -237,9 +237,10 @@ def test_continuous_limit_is_navier_stokes(prandtl):
     assert np.allclose(out[10:20], out[20:30], rtol=0, atol=0)
 
 
-def brute_point_flux(P, dt, wl, wr):
+def brute_point_flux(P, dt, wl, wr, full_step=False):
     """Independent implementation of the interface flux: every moment by phase-space quadrature, every
-    slope by a dense solve, the time integrals by adaptive quadrature of the time functions."""
+    slope by a dense solve, the time integrals by adaptive quadrature of the time functions.
+    full_step: also return the time-integrated flux over the whole step, Fbar(dt)."""
     gamma = P.gamma
     sides = [wl, wr]
     prim, pres, Qh, Qf, a = [], [], [], [], []
@@ -302,6 +303,8 @@ def brute_point_flux(P, dt, wl, wr):
     tau0 = P.tau_c * jump * dt
     w = math.exp(-dt / tau0) if tau0 > 0 else 0.0
     eul = [-rho[s] * Qf[s].mom(adotu(Qf[s], a[s])) for s in range(2)]
+    if full_step:
+        return Fb[1]
     return np.concatenate([Fn, Ft, (1 - w) * Qn + w * wl[:5], (1 - w) * Qt + w * eul[0],
                            (1 - w) * Qn + w * wr[:5], (1 - w) * Qt + w * eul[1]])
 
@@ -328,3 +331,24 @@ def test_flux_vs_bruteforce_quadrature(case):
     assert err.max() <= 1e-9, (np.argmax(err), got, ref)
     # the two sides differ exactly where the pressure jump switches the l/r model on
     assert not np.allclose(got[10:20], got[20:30])
+
+
+@pytest.mark.parametrize("case", ["viscous", "inviscid", "strong_jump"])
+def test_linearised_flux_reproduces_the_full_step_integral(case):
+    """P5c: dt F^n + dt^2/2 F_t^n equals the time integral of the interface flux over the whole step,
+    Fbar(dt) (Sec. 2: F^n and F_t^n are fixed by Fbar(dt/2) and Fbar(dt)).  GKS-2nd's one-stage
+    update Q^{n+1} = Q^n + dt L + dt^2/2 L_t rests on this identity.  Fbar(dt) comes from the
+    independent phase-space / adaptive time quadrature; Prandtl number 1 (the heat-flux correction
+    acts on F^n alone)."""
+    rng = np.random.default_rng({"viscous": 11, "inviscid": 12, "strong_jump": 13}[case])
+    if case == "inviscid":
+        P = oracle.make_params(8, 8, 8, 1, 1, 1, gamma=GAMMA, mu0=0.0, tau_eps=0.05)
+    else:
+        P = oracle.make_params(8, 8, 8, 1, 1, 1, gamma=GAMMA, mu0=0.01)
+    dt = 0.02
+    wl = _random_side(rng, (1.0, 0.5, 0.1, -0.3, 1.0))
+    wr = _random_side(rng, (0.3, -0.2, 0.4, 0.1, 0.4) if case == "strong_jump" else (1.03, 0.47, 0.12, -0.28, 0.98))
+    out = oracle.point_flux(P, dt, wl, wr)
+    fbar = brute_point_flux(P, dt, wl, wr, full_step=True)
+    lhs = dt * out[0:5] + 0.5 * dt * dt * out[5:10]
+    assert np.allclose(lhs, fbar, rtol=1e-9, atol=1e-11 * np.abs(fbar).max()), (lhs, fbar)

@@ -6,8 +6,11 @@
 * Gauss-point values converge at fifth order and derivatives at fourth order on smooth data;
 * GENO special cases: constant and linear data give chi = 1 and exact values; a jump gives chi ~ 0
   and the blend falls back to the averaged linear sub-stencil polynomials;
-* GKS-2nd: central slopes reproduce linear data; the Venkatakrishnan limiter is 1 on linear data
-  and clips at an extremum.
+* GKS-2nd (Sec. 3.3): central slopes reproduce linear data, and the Venkatakrishnan factor is 1
+  there; with eps = 0 the limited face values never leave the range of the 7-cell stencil (the
+  factor phi(y) = (y^2 + 2y)/(y^2 + y + 2) of y = Delta1/Delta2 never exceeds y) and an extremum
+  cell keeps its average on every face; a hand-worked case fixes eps^2 = (K h)^3 and the sign rule
+  of Delta1; phi is the minimum over the six face midpoints.
 """
 import math
 
@@ -237,3 +240,108 @@ def test_geno_scale_definition():
     assert oracle.geno_scale(q5, 4) == 2.5 ** 2
     for v in (1, 2, 3):
         assert oracle.geno_scale(q5, v) == 2 * 1.2 * 2.5
+
+
+# ---------------------------------------------------------------------------------------------------
+# GKS-2nd P^1 and the Venkatakrishnan limiter (Sec. 3.3, reading R13).  q7 = (cell, -x, +x, -y, +y,
+# -z, +z); faces in the same order as the neighbours.
+FACE_SIGN = np.array([-0.5, 0.5, -0.5, 0.5, -0.5, 0.5])
+
+
+def test_gks2_linear_data_exact_and_unlimited():
+    rng = np.random.default_rng(21)
+    for _ in range(20):
+        h = rng.uniform(0.05, 0.4, size=3)
+        grad = rng.normal(size=3)
+        q0 = rng.normal()
+        q7 = np.array([q0] + [q0 + sgn * grad[e] * h[e] for e in range(3) for sgn in (-1.0, 1.0)])
+        for limited in (0, 1):
+            P = oracle.make_params(8, 8, 8, 1, 1, 1, vk_k=rng.uniform(0.0, 3.0))
+            out, phi = oracle.recon_cell_gks2(P, q7, h, limited)
+            # the direction of the largest slope has Delta1 = 2 Delta2 exactly, where the factor
+            # is 1 in exact arithmetic
+            assert abs(phi - 1.0) <= 1e-14
+            for f in range(6):
+                e = f // 2
+                assert abs(out[f, 0] - (q0 + FACE_SIGN[f] * grad[e] * h[e])) <= 1e-14 * (1 + abs(q0))
+                assert np.allclose(out[f, 1:], grad, rtol=1e-13, atol=1e-13)
+    # constant data: no slope, factor 1
+    out, phi = oracle.recon_cell_gks2(oracle.make_params(8, 8, 8, 1, 1, 1), np.full(7, 2.5), np.ones(3), 1)
+    assert phi == 1.0 and np.all(out[:, 0] == 2.5) and np.all(out[:, 1:] == 0.0)
+
+
+def test_vk_without_eps_keeps_face_values_in_the_stencil_range():
+    """eps = 0 (K = 0): the limited value at every face midpoint lies in [min q7, max q7]."""
+    P = oracle.make_params(8, 8, 8, 1, 1, 1, vk_k=0.0)
+    rng = np.random.default_rng(22)
+    h = np.array([0.1, 0.2, 0.15])
+    clipped = 0
+    for _ in range(400):
+        q7 = rng.normal(size=7) * rng.uniform(0.01, 10.0)
+        out, phi = oracle.recon_cell_gks2(P, q7, h, 1)
+        lo, hi = q7.min(), q7.max()
+        tol = 1e-14 * np.abs(q7).max()
+        assert np.all(out[:, 0] >= lo - tol) and np.all(out[:, 0] <= hi + tol), (q7, out[:, 0])
+        unl, _ = oracle.recon_cell_gks2(P, q7, h, 0)
+        clipped += (unl[:, 0].min() < lo - tol) or (unl[:, 0].max() > hi + tol)
+    assert clipped > 100  # the unlimited P^1 does overshoot on such data
+
+
+def test_vk_extremum_cell_keeps_its_average():
+    """A strict local maximum (or minimum) with eps = 0: Delta1 = 0 on the faces the slope points
+    up, so phi = 0 and every face takes the cell average."""
+    P = oracle.make_params(8, 8, 8, 1, 1, 1, vk_k=0.0)
+    rng = np.random.default_rng(23)
+    for sign in (1.0, -1.0):
+        q7 = np.concatenate([[sign * 2.0], sign * rng.uniform(0.0, 1.5, size=6)])
+        out, phi = oracle.recon_cell_gks2(P, q7, np.ones(3), 1)
+        assert phi == 0.0
+        assert np.all(out[:, 0] == q7[0]) and np.all(out[:, 1:] == 0.0)
+
+
+def test_vk_hand_worked_case():
+    """q7 = (1; 0, 4 along x; 1, 1, 1, 1), cubic cells h = 1/4, K = 2, so eps^2 = (K h)^3 = 1/8.
+    x slope b = (4 - 0)/2 = 2 (per unit of the normalised coordinate).
+      -x face: Delta2 = -1 < 0, so Delta1 = min - Q0 = -1:
+               phi = (1 + 1/8 + 2) / (1 + 2 + 1 + 1/8) = 25/33;
+      +x face: Delta2 = +1, Delta1 = max - Q0 = 3: (9 + 1/8 + 6)/(9 + 2 + 3 + 1/8) = 121/113 > 1;
+      y, z faces: Delta2 = 0, factor 1.
+    So phi = 25/33: face values 1 -+ 25/33, d/dx = (25/33) 2 / h."""
+    P = oracle.make_params(8, 8, 8, 1, 1, 1, vk_k=2.0)
+    h = np.full(3, 0.25)
+    out, phi = oracle.recon_cell_gks2(P, [1, 0, 4, 1, 1, 1, 1], h, 1)
+    assert abs(phi - 25.0 / 33.0) <= 1e-15
+    assert abs(out[0, 0] - (1 - 25.0 / 33.0)) <= 1e-15 and abs(out[1, 0] - (1 + 25.0 / 33.0)) <= 1e-15
+    assert np.all(out[2:, 0] == 1.0)
+    assert abs(out[0, 1] - 25.0 / 33.0 * 2 / 0.25) <= 1e-13 and np.all(out[:, 2:] == 0.0)
+    # the same data with eps^2 read as (K h)^2 = 1/4 would give 13/17
+    assert abs(phi - 13.0 / 17.0) > 5e-3
+
+
+def _vk_face_factor(d1, d2, e2):
+    return 1.0 if d2 == 0.0 else ((d1 * d1 + e2) + 2 * d1 * d2) / (d1 * d1 + 2 * d2 * d2 + d1 * d2 + e2)
+
+
+def test_vk_factor_is_the_minimum_over_the_six_faces():
+    """Every face scales its slope by one common phi, the smallest of the six face factors, so the
+    ratio (face value - Q0) / (face offset x slope) is the same on all faces."""
+    rng = np.random.default_rng(24)
+    K = 1.0
+    h = np.full(3, 0.1)
+    P = oracle.make_params(8, 8, 8, 1, 1, 1, vk_k=K)
+    seen_different = 0
+    for _ in range(100):
+        q7 = rng.normal(size=7)
+        out, phi = oracle.recon_cell_gks2(P, q7, h, 1)
+        b = np.array([0.5 * (q7[2 + 2 * e] - q7[1 + 2 * e]) for e in range(3)])
+        e2 = (K * 0.1) ** 3
+        fac = []
+        for f in range(6):
+            d2 = FACE_SIGN[f] * b[f // 2]
+            d1 = (q7.max() - q7[0]) if d2 > 0 else (q7.min() - q7[0])
+            fac.append(_vk_face_factor(d1, d2, e2))
+        assert abs(phi - min(1.0, min(fac))) <= 1e-14
+        for f in range(6):
+            assert abs(out[f, 0] - (q7[0] + phi * FACE_SIGN[f] * b[f // 2])) <= 1e-14
+        seen_different += np.ptp(np.minimum(fac, 1.0)) > 1e-3
+    assert seen_different > 50
