@@ -49,7 +49,7 @@ enum { CGKS_RECON_LINEAR = 0, CGKS_RECON_NONLINEAR = 1, CGKS_RECON_LEARNED = 2 }
 /* FP64: every step in double.  FP32_BULK: reconstruction, flux and gradient state in float;
  * cell averages, their stage accumulations, Gauss-point states and cons->prim in double. */
 enum { CGKS_PREC_FP64 = 0, CGKS_PREC_FP32_BULK = 1 };
-enum { CGKS_IC_VORTEX2D = 0, CGKS_IC_TGV = 1, CGKS_IC_TGV_SUPERSONIC = 2 };
+enum { CGKS_IC_VORTEX2D = 0, CGKS_IC_TGV = 1, CGKS_IC_HIT = 2, CGKS_IC_TGV_SUPERSONIC = 3 };
 
 typedef struct {
   int nx, ny, nz;           /* cells per direction (>= 1; nz == 1 runs the 3-D scheme on a 2-D field);
@@ -93,10 +93,24 @@ int cgks_destroy(void* ctx);
 
 /* Set the state from host arrays q[5N], g[15N] (g may be NULL: zero gradients; GKS2 ignores g). */
 int cgks_set_state(void* ctx, const double* q, const double* g, double t, long step);
-/* Initial condition evaluated on the device: cell averages by 4x4x4 Gauss-Legendre quadrature and
- * gradients by Gauss's theorem with 4x4 points per face.  prm: VORTEX2D {strength}; TGV {Ma, rho0,
- * u0}; TGV_SUPERSONIC {Ma}.  The box is [0, l_x] x [0, l_y] x [0, l_z]. */
-int cgks_set_ic(void* ctx, int kind, const double* prm, int nprm);
+/* Initial condition (Sec. 4 test cases); the box is [0, l_x] x [0, l_y] x [0, l_z].
+ *   VORTEX2D {strength}, TGV {Ma, rho0, u0} (Sec. 4.1), TGV_SUPERSONIC {Ma} (Sec. 4.2): evaluated on
+ *     the device, cell averages by 4x4x4 Gauss-Legendre quadrature and gradients by Gauss's theorem
+ *     with 4x4 points per face; seed is ignored.
+ *   HIT {Ma_t [, k0 = 8]}: decaying isotropic turbulence generated on the host from seed (see
+ *     cgks_ic_host) and copied in.
+ * EINVAL for an unknown kind, missing parameters, or a HIT grid that cgks_ic_host rejects. */
+int cgks_set_ic(void* ctx, int kind, const double* prm, int nprm, uint64_t seed);
+/* Host evaluation of a host-generated initial condition into caller arrays q[5N], g[15N] (the layout
+ * of cgks_set_state); no device work and no context.  Only CGKS_IC_HIT: a cubic box (l_x = l_y = l_z,
+ * nx = ny = nz a power of two); a seeded solenoidal velocity field with spectrum
+ * E(k) ~ k^4 exp(-2 k^2 / k0^2) on the integer wavenumbers 1 <= |k| <= n/2 of the box, exact cell
+ * averages and cell-averaged gradients, scaled to u_rms = 1 per component; rho = 1 and uniform
+ * p = c^2 / gamma with c = sqrt(3) / Ma_t.  The white noise comes from a counter-based generator
+ * (SplitMix64 outputs, Box-Muller normals), so the field is a function of (n, k0, seed) alone.
+ * EINVAL for other kinds, a non-cubic or non-power-of-two grid, Ma_t <= 0 or k0 <= 0. */
+int cgks_ic_host(const cgks_params* p, int kind, const double* prm, int nprm, uint64_t seed, double* q,
+                 double* g);
 /* Copy the state to host arrays (double).  Synchronous. */
 int cgks_get_state(void* ctx, double* q, double* g, double* t, long* step);
 
@@ -111,6 +125,25 @@ int cgks_compute_dt(void* ctx, double cfl, double* dt);
 int cgks_step(void* ctx, int nsteps, double cfl, double t_stop, int* steps_done, double* t_now);
 /* Advance nsteps steps of the given dt (no CFL evaluation). */
 int cgks_step_fixed(void* ctx, int nsteps, double dt);
+/* One stage of a time step of size dt (Sec. 3.4), for drivers that exchange sub-domain halos between
+ * the two stages.  CGKS-5th: stage 1 builds Q*, grad Q* and the stage-1 sums from the state; stage 2
+ * completes the step (t += dt, step += 1).  GKS-2nd: stage 1 is the whole step; stage 2 is EINVAL.
+ * EINVAL also for dt <= 0.  The learned indicator runs in stage 1.  Synchronous. */
+int cgks_stage_advance(void* ctx, int stage, double dt);
+/* Halo copy between two contexts on one device that hold z-neighbouring sub-domains of one periodic
+ * box, as a domain decomposition of the sweep needs between its stages (the paper runs its solver on
+ * several GPUs by domain decomposition, Sec. 4).  Each context's grid is nx x ny x (nz_i + 2h): nz_i
+ * interior z-planes between h ghost planes below and h above, with l_z = (nz_i + 2h) h_z for the common
+ * cell size h_z.  The call copies the top h interior planes of `lower` into the bottom ghost planes of
+ * `upper` and the bottom h interior planes of `upper` into the top ghost planes of `lower`, for the
+ * state the next stage reads: which = 0 the step's state (Q, grad Q), which = 1 the first stage's
+ * output (Q*, grad Q*; CGKS-5th only).  A driver of M sub-domains calls it for each pair (i, i+1 mod M)
+ * before each stage and before the time-step reduction; the step's dt is the minimum of the
+ * sub-domains' cgks_compute_dt.  With h >= 2 (3 with the learned indicator, whose features reach two
+ * cells) every interior cell then gets the result of the undivided box bit for bit; the ghost planes'
+ * own results are discarded by the next copy.  EINVAL if the grids, precisions or schemes differ, for
+ * h < 1, nz_i < h or which outside {0, 1}; ESTATE before both have a state.  Synchronous. */
+int cgks_halo_exchange_z(void* lower, void* upper, int h, int which);
 /* One stage operator on the current state with step size dt, copied to host arrays (any may be
  * NULL): L[5N], dL/dt[5N] and, for CGKS5, the Gauss-theorem sums sqn[15N], sqt[15N] of the
  * interface values and of their time derivatives.  The state is unchanged. */

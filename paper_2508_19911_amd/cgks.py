@@ -17,14 +17,15 @@ LIB_PATH = os.path.join(HERE, "libcgks.so")
 SCHEME_CGKS5, SCHEME_GKS2 = 0, 1
 RECON_LINEAR, RECON_NONLINEAR, RECON_LEARNED = 0, 1, 2
 PREC_FP64, PREC_FP32_BULK = 0, 1
-IC_VORTEX2D, IC_TGV, IC_TGV_SUPERSONIC = 0, 1, 2
+IC_VORTEX2D, IC_TGV, IC_HIT, IC_TGV_SUPERSONIC = 0, 1, 2, 3
 MLP_NPARAM = 4225
 ERRORS = {0: "ok", -1: "EINVAL", -2: "EWORKSPACE", -3: "EDEVICE", -4: "ENONPHYSICAL", -5: "ESTATE"}
 
 # every entry point declared in include/cgks.h
 SYMBOLS = [
-    "cgks_workspace_bytes", "cgks_create", "cgks_destroy", "cgks_set_state", "cgks_set_ic",
+    "cgks_workspace_bytes", "cgks_create", "cgks_destroy", "cgks_set_state", "cgks_set_ic", "cgks_ic_host",
     "cgks_get_state", "cgks_compute_dt", "cgks_step", "cgks_step_fixed", "cgks_stage", "cgks_stage_sampled",
+    "cgks_stage_advance", "cgks_halo_exchange_z",
     "cgks_diagnostics", "cgks_diagnostics_quad", "cgks_get_flags", "cgks_indicator_set", "cgks_indicator_get",
     "cgks_features", "cgks_indicator_logits", "cgks_labels", "cgks_indicator_train",
     "cgks_indicator_grad", "cgks_timing_enable", "cgks_timing_read", "cgks_debug_point_flux",
@@ -79,7 +80,10 @@ def load():
     L.cgks_create.argtypes = [pp, P, Z, P, ctypes.POINTER(P)]
     L.cgks_destroy.argtypes = [P]
     L.cgks_set_state.argtypes = [P, P, P, D, ctypes.c_long]
-    L.cgks_set_ic.argtypes = [P, I, P, I]
+    L.cgks_set_ic.argtypes = [P, I, P, I, ctypes.c_uint64]
+    L.cgks_ic_host.argtypes = [pp, I, P, I, ctypes.c_uint64, P, P]
+    L.cgks_stage_advance.argtypes = [P, I, D]
+    L.cgks_halo_exchange_z.argtypes = [P, P, I, I]
     L.cgks_get_state.argtypes = [P, P, P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)]
     L.cgks_compute_dt.argtypes = [P, D, ctypes.POINTER(D)]
     L.cgks_step.argtypes = [P, I, D, D, ctypes.POINTER(I), ctypes.POINTER(D)]
@@ -113,6 +117,16 @@ def _p(a):
 def _check(what, rc):
     if rc != 0:
         raise CgksError(what, rc)
+
+
+def ic_host(case, kind, prm=(), seed=0):
+    """cgks_ic_host: a host-generated initial condition (q[5][N], g[15][N]) for the grid of case."""
+    p = params_from_case(case)
+    a = np.ascontiguousarray(prm, dtype=np.float64)
+    q = np.empty((5, case.N)); g = np.empty((15, case.N))
+    _check("cgks_ic_host", load().cgks_ic_host(ctypes.byref(p), int(kind), _p(a) if a.size else None, a.size,
+                                               int(seed), _p(q), _p(g)))
+    return q, g
 
 
 def params_from_case(case, precision=PREC_FP64, indicator_logit=0.0) -> Params:
@@ -160,9 +174,10 @@ class Solver:
         g = None if g is None else np.ascontiguousarray(g, dtype=np.float64).reshape(15, -1)
         _check("cgks_set_state", load().cgks_set_state(self.h, _p(q), _p(g), float(t), int(step)))
 
-    def set_ic(self, kind, prm=()):
+    def set_ic(self, kind, prm=(), seed=0):
         a = np.ascontiguousarray(prm, dtype=np.float64)
-        _check("cgks_set_ic", load().cgks_set_ic(self.h, int(kind), _p(a) if a.size else None, a.size))
+        _check("cgks_set_ic", load().cgks_set_ic(self.h, int(kind), _p(a) if a.size else None, a.size,
+                                                 int(seed)))
 
     def get_state(self):
         q = np.empty((5, self.N)); g = np.empty((15, self.N))
@@ -182,6 +197,13 @@ class Solver:
         if check:
             _check("cgks_step", rc)
         return rc, done.value, tn.value
+
+    def stage_advance(self, stage, dt):
+        _check("cgks_stage_advance", load().cgks_stage_advance(self.h, int(stage), float(dt)))
+
+    def halo_exchange_z(self, upper, h, which):
+        """cgks_halo_exchange_z(self = the lower sub-domain, upper, h, which)"""
+        _check("cgks_halo_exchange_z", load().cgks_halo_exchange_z(self.h, upper.h, int(h), int(which)))
 
     def step_fixed(self, nsteps, dt):
         _check("cgks_step_fixed", load().cgks_step_fixed(self.h, int(nsteps), float(dt)))

@@ -11,6 +11,7 @@
 
 #include "../../include/cgks.h"
 #include "kernels.hpp"
+#include "hit_ic.hpp"
 #include "mlp.hpp"
 
 using namespace cgks;
@@ -22,7 +23,9 @@ thread_local std::string g_last_error;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t Q, G, Qs, Gs, Acc, GQn, C, F, flags, red, scal, mlp, total;
+  // F: the FP64 face planes (F^n, 5 per direction); FT: the T face planes (F_t, and for CGKS-5th the
+  // interface values: 25 per direction; 5 for GKS-2nd); Fend: the end of both (a scratch region)
+  size_t Q, G, Qs, Gs, Acc, GQn, C, F, FT, Fend, flags, red, scal, mlp, total;
 };
 
 bool valid(const cgks_params* p) {
@@ -64,7 +67,9 @@ Layout layout(const cgks_params* p) {
                      : 15 * N * ts;
   if (cbytes < 64 * N * 4) cbytes = 64 * N * 4;
   L.C = take(cbytes);
-  L.F = take((c5 ? 90 : 30) * N * ts);
+  L.F = take(15 * N * 8);
+  L.FT = take((c5 ? 75 : 15) * N * ts);
+  L.Fend = o;
   L.flags = take(N);
   L.red = take(nblk * 16 * 8);
   L.scal = take(64 * 8);
@@ -197,18 +202,19 @@ int stage5(Ctx& c, const double* Q, const T* G, const double* ctl) {
   const dim3 grid(c.nblk), blk(BLK);
   const dim3 fgrid((unsigned)((c.g.N + FLUX_FACES - 1) / FLUX_FACES)), fblk(FLUX_BLK);
   const T* C = c.at<T>(c.L.C);
-  T* F = c.at<T>(c.L.F);
+  double* Fd = c.at<double>(c.L.F);
+  T* Fb = c.at<T>(c.L.FT);
   {
     TimedScope t0(c, CGKS_KC_FLUX);
-    k_flux5<T, 0><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, ctl);
+    k_flux5<T, 0><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, Fd, Fb, c.fp, ctl);
   }
   {
     TimedScope t1(c, CGKS_KC_FLUX);
-    k_flux5<T, 1><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, ctl);
+    k_flux5<T, 1><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, Fd, Fb, c.fp, ctl);
   }
   {
     TimedScope t2(c, CGKS_KC_FLUX);
-    k_flux5<T, 2><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, F, c.fp, ctl);
+    k_flux5<T, 2><<<fgrid, fblk, 0, c.stream>>>(c.g, Q, C, Fd, Fb, c.fp, ctl);
   }
   LAUNCHCK("k_flux5");
   Stage5Out o;
@@ -220,7 +226,7 @@ int stage5(Ctx& c, const double* Q, const T* G, const double* ctl) {
   o.G = c.at<T>(c.L.G);
   {
     TimedScope tu(c, CGKS_KC_UPDATE);
-    k_update5<T, STAGE><<<grid, blk, 0, c.stream>>>(c.g, F, c.at<double>(c.L.Q), o, ctl);
+    k_update5<T, STAGE><<<grid, blk, 0, c.stream>>>(c.g, Fd, Fb, c.at<double>(c.L.Q), o, ctl);
   }
   LAUNCHCK("k_update5");
   return CGKS_OK;
@@ -231,7 +237,8 @@ int stage2(Ctx& c, const double* ctl) {
   const dim3 grid(c.nblk), blk(BLK);
   double* Q = c.at<double>(c.L.Q);
   T* S = c.at<T>(c.L.C);
-  T* F = c.at<T>(c.L.F);
+  double* Fd = c.at<double>(c.L.F);
+  T* Fb = c.at<T>(c.L.FT);
   {
     TimedScope ts(c, CGKS_KC_COEF);
     if (c.p.recon == CGKS_RECON_NONLINEAR)
@@ -241,19 +248,19 @@ int stage2(Ctx& c, const double* ctl) {
   }
   {
     TimedScope t0(c, CGKS_KC_FLUX);
-    k_flux2<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, ctl);
+    k_flux2<T, 0><<<grid, blk, 0, c.stream>>>(c.g, Q, S, Fd, Fb, c.fp, ctl);
   }
   {
     TimedScope t1(c, CGKS_KC_FLUX);
-    k_flux2<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, ctl);
+    k_flux2<T, 1><<<grid, blk, 0, c.stream>>>(c.g, Q, S, Fd, Fb, c.fp, ctl);
   }
   {
     TimedScope t2(c, CGKS_KC_FLUX);
-    k_flux2<T, 2><<<grid, blk, 0, c.stream>>>(c.g, Q, S, F, c.fp, ctl);
+    k_flux2<T, 2><<<grid, blk, 0, c.stream>>>(c.g, Q, S, Fd, Fb, c.fp, ctl);
   }
   {
     TimedScope tu(c, CGKS_KC_UPDATE);
-    k_update2<T, DEBUG><<<grid, blk, 0, c.stream>>>(c.g, F, Q, c.at<double>(c.L.Acc),
+    k_update2<T, DEBUG><<<grid, blk, 0, c.stream>>>(c.g, Fd, Fb, Q, c.at<double>(c.L.Acc),
                                                      c.at<double>(c.L.Qs), ctl);
   }
   LAUNCHCK("gks2 stage");
@@ -474,11 +481,33 @@ int cgks_set_state(void* ctx, const double* q, const double* g, double t, long s
   return CGKS_OK;
 }
 
-int cgks_set_ic(void* ctx, int kind, const double* prm, int nprm) {
+int cgks_ic_host(const cgks_params* p, int kind, const double* prm, int nprm, uint64_t seed, double* q,
+                 double* g) {
+  if (!valid(p) || !q || !g) return CGKS_EINVAL;
+  if (kind != CGKS_IC_HIT) return CGKS_EINVAL;
+  const int n = p->nx;
+  if (p->ny != n || p->nz != n || n < 2 || (n & (n - 1)) != 0) return CGKS_EINVAL;
+  if (!(p->lx == p->ly && p->ly == p->lz)) return CGKS_EINVAL;
+  if (!prm || nprm < 1 || !(prm[0] > 0.0)) return CGKS_EINVAL;
+  const double k0 = nprm > 1 ? prm[1] : 8.0;
+  if (!(k0 > 0.0)) return CGKS_EINVAL;
+  cgks::hit::field(n, p->lx, p->gamma, prm[0], k0, seed, q, g);
+  return CGKS_OK;
+}
+
+int cgks_set_ic(void* ctx, int kind, const double* prm, int nprm, uint64_t seed) {
   if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
+  if (kind == CGKS_IC_HIT) {
+    // generated on the host, then set like any host state
+    const size_t N = c.g.N;
+    std::vector<double> q(5 * N), g(15 * N);
+    const int rc = cgks_ic_host(&c.p, kind, prm, nprm, seed, q.data(), g.data());
+    if (rc) return rc;
+    return cgks_set_state(ctx, q.data(), g.data(), 0.0, 0);
+  }
   ICParams ip;
-  ip.kind = kind;
+  ip.kind = kind == CGKS_IC_TGV_SUPERSONIC ? 2 : kind;
   ip.gamma = c.p.gamma;
   ip.a0 = ip.a1 = ip.a2 = 0.0;
   if (kind == CGKS_IC_VORTEX2D) {
@@ -628,6 +657,66 @@ int cgks_step_fixed(void* ctx, int nsteps, double dt) {
   return CGKS_OK;
 }
 
+int cgks_stage_advance(void* ctx, int stage, double dt) {
+  if (!ctx) return CGKS_EINVAL;
+  Ctx& c = *static_cast<Ctx*>(ctx);
+  if (!c.have_state) return CGKS_ESTATE;
+  if (c.p.recon == CGKS_RECON_LEARNED && !c.have_mlp) return CGKS_ESTATE;
+  const bool gks2 = c.p.scheme == CGKS_SCHEME_GKS2;
+  if (!(dt > 0.0) || stage < 1 || stage > (gks2 ? 1 : 2)) return CGKS_EINVAL;
+  const bool f64 = c.p.precision == CGKS_PREC_FP64;
+  const double* ctl = set_dt(c, dt);
+  int rc;
+  if (gks2)
+    rc = f64 ? stage2<double, 0>(c, ctl) : stage2<float, 0>(c, ctl);
+  else if (stage == 1)
+    rc = f64 ? stage5<double, 1>(c, c.at<double>(c.L.Q), c.at<double>(c.L.G), ctl)
+             : stage5<float, 1>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G), ctl);
+  else
+    rc = f64 ? stage5<double, 2>(c, c.at<double>(c.L.Qs), c.at<double>(c.L.Gs), ctl)
+             : stage5<float, 2>(c, c.at<double>(c.L.Qs), c.at<float>(c.L.Gs), ctl);
+  if (rc) return rc;
+  if (gks2 || stage == 2) {
+    c.t += dt;
+    c.step += 1;
+  }
+  HIPCK(hipStreamSynchronize(c.stream));
+  return CGKS_OK;
+}
+
+int cgks_halo_exchange_z(void* lower, void* upper, int h, int which) {
+  if (!lower || !upper || lower == upper) return CGKS_EINVAL;
+  Ctx& a = *static_cast<Ctx*>(lower);
+  Ctx& b = *static_cast<Ctx*>(upper);
+  if (!a.have_state || !b.have_state) return CGKS_ESTATE;
+  if (a.g.nx != b.g.nx || a.g.ny != b.g.ny || a.p.precision != b.p.precision || a.p.scheme != b.p.scheme)
+    return CGKS_EINVAL;
+  if (h < 1 || which < 0 || which > 1 || a.g.nz < 3 * h || b.g.nz < 3 * h) return CGKS_EINVAL;
+  if (which == 1 && a.p.scheme == CGKS_SCHEME_GKS2) return CGKS_EINVAL;
+  const size_t plane = (size_t)a.g.nx * a.g.ny;
+  const size_t ts = a.p.precision == CGKS_PREC_FP64 ? 8 : 4;
+  const size_t oq_a = which ? a.L.Qs : a.L.Q, og_a = which ? a.L.Gs : a.L.G;
+  const size_t oq_b = which ? b.L.Qs : b.L.Q, og_b = which ? b.L.Gs : b.L.G;
+  const int nza = a.g.nz;
+  const int ng = a.p.scheme == CGKS_SCHEME_CGKS5 ? 15 : 0;  // GKS-2nd carries no gradients
+  // both streams' work so far is complete before the copies; the copies complete before return
+  HIPCK(hipStreamSynchronize(b.stream));
+  HIPCK(hipStreamSynchronize(a.stream));
+  for (int f = 0; f < 5 + ng; ++f) {
+    const bool isq = f < 5;
+    const size_t es = isq ? 8 : ts;
+    const size_t fa = (isq ? oq_a : og_a) + (size_t)(isq ? f : f - 5) * a.g.N * es;
+    const size_t fb = (isq ? oq_b : og_b) + (size_t)(isq ? f : f - 5) * b.g.N * es;
+    // lower's top interior planes -> upper's bottom ghosts; upper's bottom interior -> lower's top ghosts
+    HIPCK(hipMemcpyAsync(b.ws + fb, a.ws + fa + (size_t)(nza - 2 * h) * plane * es, h * plane * es,
+                         hipMemcpyDeviceToDevice, a.stream));
+    HIPCK(hipMemcpyAsync(a.ws + fa + (size_t)(nza - h) * plane * es, b.ws + fb + (size_t)h * plane * es,
+                         h * plane * es, hipMemcpyDeviceToDevice, a.stream));
+  }
+  HIPCK(hipStreamSynchronize(a.stream));
+  return CGKS_OK;
+}
+
 int cgks_stage(void* ctx, double dt, double* L, double* Lt, double* sqn, double* sqt) {
   if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
@@ -682,8 +771,7 @@ int cgks_stage_sampled(void* ctx, double dt, const long* cells, long n, double* 
     if (cells[m] < 0 || cells[m] >= c.g.N) return CGKS_EINVAL;
   // staging in the face planes, free once the stage has been assembled: indices, then 40 doubles
   // per sampled cell
-  const size_t ts = c.p.precision == CGKS_PREC_FP64 ? 8 : 4;
-  const size_t fbytes = (c5 ? 90 : 30) * (size_t)c.g.N * ts;
+  const size_t fbytes = c.L.Fend - c.L.F;
   const size_t ibytes = ((size_t)n * 4 + 255) & ~(size_t)255;
   if (ibytes + 40 * (size_t)n * 8 > fbytes) return CGKS_EINVAL;
   const bool f64 = c.p.precision == CGKS_PREC_FP64;
@@ -903,8 +991,7 @@ int cgks_debug_point_flux(void* ctx, double dt, long n, const double* wl, const 
   if (!ctx) return CGKS_EINVAL;
   Ctx& c = *static_cast<Ctx*>(ctx);
   if (n < 1 || !wl || !wr || !out || !(dt > 0.0)) return CGKS_EINVAL;
-  const size_t cap = (c.p.scheme == CGKS_SCHEME_CGKS5 ? 90 : 30) * (size_t)c.g.N *
-                     (c.p.precision == CGKS_PREC_FP64 ? 8 : 4);
+  const size_t cap = c.L.Fend - c.L.F;
   if ((size_t)n * 70 * 8 > cap) return CGKS_EINVAL;
   double* d = c.at<double>(c.L.F);
   HIPCK(hipMemcpyAsync(d, wl, n * 20 * 8, hipMemcpyHostToDevice, c.stream));

@@ -9,48 +9,12 @@ namespace cgks {
 
 // Math in the bulk type.  FP64: the device library's correctly-rounded / few-ulp routines.  The FP32
 // form uses the hardware square root, reciprocal square root and base-2 exponential (about 1 ulp;
-// e^x = 2^(x log2 e) adds a relative error of about |x| 6e-8 from the rounded product), and the
-// library's erfc.  The host build of the same code (tests) uses the C library throughout.
+// e^x = 2^(x log2 e) adds a relative error of about |x| 6e-8 from the rounded product).  The host
+// build of the same code (tests) uses the C library throughout.
 __host__ __device__ __forceinline__ double dsqrt(double x) { return sqrt(x); }
 __host__ __device__ __forceinline__ double dexp(double x) { return exp(x); }
 __host__ __device__ __forceinline__ double dexpm1(double x) { return expm1(x); }
 __host__ __device__ __forceinline__ double derfc(double x) { return erfc(x); }
-#ifdef __HIP_DEVICE_COMPILE__
-__device__ __forceinline__ float dexp_arg(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
-#endif
-// erfc in the FP32 form: for |x| < 1/2, 1 - erf(x) with the Maclaurin series of erf to x^13
-// (truncation below 2e-8); elsewhere the Chebyshev-fitted form t exp(-z^2 + P(t)), t = 1/(1 + z/2),
-// z = |x|, of Press et al., Numerical Recipes (2nd ed., Sec. 6.2; fractional error below 1.2e-7 in
-// exact arithmetic), reflected by erfc(-z) = 2 - erfc(z).  Max relative error about 4 ulp near 0
-// and 2e-6 for x > 2, where erfc < 0.005 (absolute error below 1e-8).
-__host__ __device__ __forceinline__ float derfc(float x) {
-#ifdef __HIP_DEVICE_COMPILE__
-  const float z = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * z);
-  float p = 0.17087277f;
-  p = p * t - 0.82215223f;
-  p = p * t + 1.48851587f;
-  p = p * t - 1.13520398f;
-  p = p * t + 0.27886807f;
-  p = p * t - 0.18628806f;
-  p = p * t + 0.09678418f;
-  p = p * t + 0.37409196f;
-  p = p * t + 1.00002368f;
-  const float far = t * dexp_arg(-z * z - 1.26551223f + t * p);
-  const float x2 = x * x;
-  float q = 1.0f / 9360.0f;
-  q = q * x2 - 1.0f / 1320.0f;
-  q = q * x2 + 1.0f / 216.0f;
-  q = q * x2 - 1.0f / 42.0f;
-  q = q * x2 + 0.1f;
-  q = q * x2 - 1.0f / 3.0f;
-  q = q * x2 + 1.0f;
-  const float near = 1.0f - 1.12837916709551257f * x * q;  // 2/sqrt(pi)
-  return z < 0.5f ? near : (x >= 0.0f ? far : 2.0f - far);
-#else
-  return erfcf(x);
-#endif
-}
 __host__ __device__ __forceinline__ float dsqrt(float x) {
 #ifdef __HIP_DEVICE_COMPILE__
   return __builtin_amdgcn_sqrtf(x);
@@ -91,6 +55,76 @@ __host__ __device__ __forceinline__ float dexpm1(float x) {
   return expm1f(x);
 #endif
 }
+// 1/sqrt(x) in FP64: the hardware FP32 estimate refined by two Newton steps (relative error of a
+// few 1e-16 for x in the normal FP32 range); the host build uses the C library.
+__host__ __device__ __forceinline__ double rsqrt64(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double y = (double)__builtin_amdgcn_rsqf((float)x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+#else
+  return 1.0 / sqrt(x);
+#endif
+}
+
+// The split at u = 0 of a Maxwellian's normal velocity (mean U, variance var = p/rho), in FP64:
+// pp = P(u > 0) = erfc(-x)/2 and pm = P(u < 0) = erfc(x)/2 with x = U/sqrt(2 var), and
+// tail = e^{-x^2} sqrt(var/(2 pi)), so that <u>_{u>0} = U pp + tail and <u>_{u<0} = U pm - tail.
+// For |x| < 1/2 (every point of a low-Mach flow) erf(x) and e^{-x^2} are their Maclaurin series,
+// truncated below 1e-17; elsewhere the library's erfc and exp.  D is double (or a counting type).
+template <class D>
+__host__ __device__ __forceinline__ void normal_split(D U, D var, D& pp, D& pm, D& tail) {
+  const D isv = rsqrt64(var);
+  const D x = U * isv * D(0.70710678118654752440);
+  const D y = -(x * x);
+  D g;
+  if (fabs(x) < D(0.5)) {
+    // erf(x) = (2/sqrt(pi)) x sum_n y^n / (n! (2n+1)), n = 0..11
+    D s = D(1.0 / 918086400.0);
+    s = s * y + D(1.0 / 76204800.0);
+    s = s * y + D(1.0 / 6894720.0);
+    s = s * y + D(1.0 / 685440.0);
+    s = s * y + D(1.0 / 75600.0);
+    s = s * y + D(1.0 / 9360.0);
+    s = s * y + D(1.0 / 1320.0);
+    s = s * y + D(1.0 / 216.0);
+    s = s * y + D(1.0 / 42.0);
+    s = s * y + D(1.0 / 10.0);
+    s = s * y + D(1.0 / 3.0);
+    s = s * y + D(1.0);
+    const D he = D(0.56418958354775628695) * x * s;  // erf(x) / 2
+    pp = D(0.5) + he;
+    pm = D(0.5) - he;
+    // e^y = sum_n y^n / n!, n = 0..12
+    g = D(1.0 / 479001600.0);
+    g = g * y + D(1.0 / 39916800.0);
+    g = g * y + D(1.0 / 3628800.0);
+    g = g * y + D(1.0 / 362880.0);
+    g = g * y + D(1.0 / 40320.0);
+    g = g * y + D(1.0 / 5040.0);
+    g = g * y + D(1.0 / 720.0);
+    g = g * y + D(1.0 / 120.0);
+    g = g * y + D(1.0 / 24.0);
+    g = g * y + D(1.0 / 6.0);
+    g = g * y + D(0.5);
+    g = g * y + D(1.0);
+    g = g * y + D(1.0);
+  } else {
+    const D c = D(0.5) * derfc(fabs(x));
+    if (x > D(0)) {
+      pm = c;
+      pp = D(1) - c;
+    } else {
+      pp = c;
+      pm = D(1) - c;
+    }
+    g = dexp(y);
+  }
+  tail = g * (var * isv) * D(0.39894228040143267794);
+}
+
 // reciprocal in the bulk type: IEEE 1/x in FP64; the hardware reciprocal (1 ulp) in the FP32 form
 __host__ __device__ __forceinline__ double drcp(double x) { return 1.0 / x; }
 __host__ __device__ __forceinline__ float drcp(float x) {

@@ -3,8 +3,8 @@
 //
 // Convention: add, sub, mul, div = 1 flop; fma = 2; sqrt, exp, expm1, erfc = 1 each (reported
 // separately as transcendentals).  Comparisons, min/max, abs and conversions are not counted.  The
-// few FP64 operations written outside the templated type (the conservative -> primitive conversion of
-// the two Gauss-point states, the Q - Q0 differences of the stencil) are added by hand below.
+// flux is instantiated with the counting type for both its bulk and its FP64 arithmetic; the FP64
+// differences Q - Q0 of the stencil, written outside the templates, are added by hand below.
 //
 // Build and run (host only, no GPU needed):
 //   hipcc -std=c++17 -O1 --offload-arch=gfx950 paper_2508_19911_amd/csrc/flopcount.hip -o flopcount
@@ -105,6 +105,15 @@ inline Fl dexp(Fl x) { return un('e', x, std::exp(x.v())); }
 inline Fl dexpm1(Fl x) { return un('x', x, std::expm1(x.v())); }
 inline Fl derfc(Fl x) { return un('r', x, std::erfc(x.v())); }
 inline Fl drcp(Fl x) { return mkf('/', Fl(1.0), x, 1.0 / x.v()); }
+// FP64 reciprocal square root of the device: a hardware estimate (1 transcendental) and two Newton
+// steps, written out so that their operations are counted
+inline Fl rsqrt64(Fl x) {
+  Fl y = un('q', x, 1.0 / std::sqrt(x.v()));
+  const Fl hx = Fl(0.5) * x;
+  y = y * fma(-(hx * y), y, Fl(1.5));
+  y = y * fma(-(hx * y), y, Fl(1.5));
+  return y;
+}
 inline Fl dfma(Fl a, Fl b, Fl c) { return fma(a, b, c); }
 }  // namespace fc
 
@@ -133,25 +142,27 @@ int main() {
   //     the flux, the 4-lane Gauss average and the 0.25 scaling of its 30 outputs
   const FluxParams fp = make_flux_params(1.4, 6.25e-4, 71.43, 0.72, 0.05, 10.0);
   double WL[5] = {1.0, 0.3, 0.1, -0.2, 180.0}, WR[5] = {1.01, 0.31, 0.09, -0.21, 180.2};
-  Fl DL[15], DR[15], out[30];
+  Fl DL[15], DR[15], VL[5], VR[5], out[25], Fn[5];
   Fl a[34];
   reset();
   for (int m = 0; m < 34; ++m) a[m] = leaf(1e-3 * (m + 1));
   Fl val[4], der[4][3];
   eval_face<1>(a, leaf(-1.0), val, der);
   const long long eval_face_flops = fc::n_flop;
-  // per face: 10 (variable, side) polynomials, each evaluated at the 4 points, plus per point
-  // Q0 + value (1) and three derivative scalings (3)
-  const long long state_face = 10 * (eval_face_flops + 4 * (1 + 3));
+  // per face: 10 (variable, side) polynomials, each evaluated at the 4 points, plus per point three
+  // derivative scalings (Q0 + value is counted inside the flux)
+  const long long state_face = 10 * (eval_face_flops + 4 * 3);
   reset();
   for (int q = 0; q < 15; ++q) {
     DL[q] = leaf(0.01 * (q + 1));
     DR[q] = leaf(0.011 * (q + 1));
   }
-  gks_flux<Fl, 30>(fp, 1e-3, WL, DL, WR, DR, out);
-  // FP64 cons->prim of the two states: 1/rho, 3 velocities, p (8), var = p/rho (1) = 13 per side;
-  // the FP64 difference and sum of the two pressures in the relative jump: 2
-  const long long flux_flops = fc::n_flop + 2 * 13 + 2;
+  for (int v = 0; v < 5; ++v) {
+    VL[v] = leaf(1e-3 * (v + 1));
+    VR[v] = leaf(-1e-3 * (v + 2));
+  }
+  gks_flux<Fl, true, Fl>(fp, 1e-3, WL, VL, DL, WR, VR, DR, Fn, out);
+  const long long flux_flops = fc::n_flop;
   const long long flux_trans = fc::n_trans;
   const long long reduce_flops = 30 * 3;  // two lane sums and the 1/4 scaling per output
 

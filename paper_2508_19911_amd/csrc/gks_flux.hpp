@@ -1,13 +1,21 @@
 // gks_flux.hpp -- gas-kinetic interface flux at one Gauss point (arXiv 2508.19911, Sec. 2).
 //
 // Device routine, templated on the bulk arithmetic type T (double, or float in the FP32-bulk
-// form).  The Gauss-point states arrive as FP64 conservative values plus T derivatives; the
-// conversion to primitive variables is done in FP64 and everything after it in T.
+// form).  The Gauss-point states arrive as FP64 conservative values plus T derivatives.
 //
 // f at the interface is eq. (flux): an equilibrium part built on g0 and the left/right parts on
 // g_l (u > 0) and g_r (u < 0).  Its time integrals over [0, dt/2] and [0, dt] give the linearised
 // f^n and f_t^n, whose moments are F^n, F_t^n (eq. deri-t-f) and Q^n, Q_t^n (eq. deri-t-q).  The
 // coefficients of the six time functions are used in closed form (no cancellation).
+//
+// Precision.  The parts of the flux whose size is that of the pressure are kept in FP64 in either
+// form: the conversion of both states to primitives, the split of each side at u = 0 and the
+// half-space sums that give the interface equilibrium state W0 and the side fluxes <u psi>, the
+// primitives of W0, its Euler flux, and the assembly of F^n, of the interface values and of the
+// Prandtl correction.  At low Mach number these are ~1/Ma^2 times larger than the variations that
+// drive the flow, so rounding them to FP32 would cost that many digits.  What stays in T are the
+// slope and time-derivative products, whose weights (tau, dt) make them small: at the scale of the
+// viscous and unsteady parts of the flux, FP32 keeps their relative precision.
 //
 // Readings where the paper defers to its references:
 //  * g0 is the half-space split of the two sides, W0 = rho_l <psi>_{l,u>0} + rho_r <psi>_{r,u<0};
@@ -19,6 +27,8 @@
 //    w = exp(-dt/tau0), tau0 = C |p_l-p_r|/(p_l+p_r) dt.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -50,42 +60,25 @@ struct FrameMom {
   T u[7], vu[4], ph[4], qq[3], vh[2];
 };
 
-// sqrt(lam) and sqrt(var) = sqrt(1 / (2 lam)); the FP32 form takes both from one reciprocal square
-// root
-template <class T>
-__host__ __device__ __forceinline__ void lam_roots(T lam, T var, T& sl, T& sv) {
-  sl = dsqrt(lam);
-  sv = dsqrt(var);
-}
-__host__ __device__ __forceinline__ void lam_roots(float lam, float, float& sl, float& sv) {
-  const float r = drsq(lam);
-  sl = lam * r;
-  sv = 0.70710678118654752f * r;
-}
-
 // normal moments by the Gaussian recursion u_k = U u_{k-1} + (k-1) var u_{k-2} (exact on a half
-// range bounded at 0 once k >= 2); HALF = +1 (u > 0), -1 (u < 0) or 0 (full range)
+// range bounded at 0 once k >= 2); HALF = 0: the full range; HALF != 0: a half range whose u_0..u_3
+// are given (computed in FP64 by the caller)
 template <int HALF, class T>
-__host__ __device__ __forceinline__ void frame_moments(const Prim<T>& p, T Kdof, FrameMom<T>& m) {
+__host__ __device__ __forceinline__ void frame_moments(const Prim<T>& p, T Kdof, FrameMom<T>& m,
+                                                       const T* u03 = nullptr) {
   const T var = p.var;
+  int k0 = 2;
   if constexpr (HALF == 0) {
     m.u[0] = T(1);
     m.u[1] = p.U;
   } else {
-    T sl, sv;
-    lam_roots(p.lam, var, sl, sv);
-    // e^{-lam U^2} / (2 sqrt(pi lam)) = e^{-lam U^2} sqrt(var / (2 pi))
-    const T tail = dexp(-p.lam * p.U * p.U) * (T(0.39894228040143267794) * sv);
-    if constexpr (HALF > 0) {
-      m.u[0] = T(0.5) * derfc(-sl * p.U);
-      m.u[1] = p.U * m.u[0] + tail;
-    } else {
-      m.u[0] = T(0.5) * derfc(sl * p.U);
-      m.u[1] = p.U * m.u[0] - tail;
-    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m.u[k] = u03[k];
+    k0 = 4;
   }
 #pragma unroll
-  for (int k = 2; k < 7; ++k) m.u[k] = p.U * m.u[k - 1] + T(k - 1) * var * m.u[k - 2];
+  for (int k = 2; k < 7; ++k)
+    if (k >= k0) m.u[k] = p.U * m.u[k - 1] + T(k - 1) * var * m.u[k - 2];
   const T hr1 = T(0.5) * (Kdof + T(2)) * var;
   const T qr2 = T(0.25) * (Kdof + T(2)) * (Kdof + T(4)) * var * var;
   const T hk4 = T(0.5) * (Kdof + T(4)) * var;
@@ -135,16 +128,6 @@ __host__ __device__ __forceinline__ void tslope_t(const FrameMom<T>& m, const T 
   o[4] = o[4] + s[AX] * m.vh[A];
 }
 
-// o (=|+=) rho <u^A psi'> = rho (u_A, u_{A+1}, 0, 0, ph_A)
-template <int A, class T>
-__host__ __device__ __forceinline__ void tpsi(const FrameMom<T>& m, T rho, T o[5]) {
-  o[0] = rho * m.u[A];
-  o[1] = rho * m.u[A + 1];
-  o[2] = T(0);
-  o[3] = T(0);
-  o[4] = rho * m.ph[A];
-}
-
 // Galilean shift by the tangential velocity (V, W), kv = (V^2 + W^2)/2:
 // lab moments R -> frame moments R' (psi4 = psi4' + V v' + W w' + kv)
 template <class T>
@@ -155,33 +138,21 @@ __host__ __device__ __forceinline__ void to_frame(const T* R, T V, T W, T kv, T 
   o[3] = R[3] - W * R[0];
   o[4] = R[4] - V * R[2] - W * R[3] + kv * R[0];
 }
-// frame moments o' -> lab, stored (SET) or added into L; ZT: o'[2] = o'[3] = 0
-template <bool SET, bool ZT = false, class T>
+// frame moments o' -> lab, stored (SET) or added into L
+template <bool SET, class T>
 __host__ __device__ __forceinline__ void from_frame(const T o[5], T V, T W, T kv, T L[5]) {
   if constexpr (SET) {
     L[0] = o[0];
     L[1] = o[1];
-    if constexpr (ZT) {
-      L[2] = V * o[0];
-      L[3] = W * o[0];
-      L[4] = o[4] + kv * o[0];
-    } else {
-      L[2] = o[2] + V * o[0];
-      L[3] = o[3] + W * o[0];
-      L[4] = o[4] + V * o[2] + W * o[3] + kv * o[0];
-    }
+    L[2] = o[2] + V * o[0];
+    L[3] = o[3] + W * o[0];
+    L[4] = o[4] + V * o[2] + W * o[3] + kv * o[0];
   } else {
     L[0] = L[0] + o[0];
     L[1] = L[1] + o[1];
-    if constexpr (ZT) {
-      L[2] = L[2] + V * o[0];
-      L[3] = L[3] + W * o[0];
-      L[4] = L[4] + o[4] + kv * o[0];
-    } else {
-      L[2] = L[2] + o[2] + V * o[0];
-      L[3] = L[3] + o[3] + W * o[0];
-      L[4] = L[4] + o[4] + V * o[2] + W * o[3] + kv * o[0];
-    }
+    L[2] = L[2] + o[2] + V * o[0];
+    L[3] = L[3] + o[3] + W * o[0];
+    L[4] = L[4] + o[4] + V * o[2] + W * o[3] + kv * o[0];
   }
 }
 
@@ -242,55 +213,127 @@ __host__ __device__ __forceinline__ T viscosity(const FluxParams& P, T Temp) {
   return T(P.mu0);
 }
 
+// conversion between the FP64 type D and the bulk type T (the identity when they are one type)
+template <class T, class D>
+__host__ __device__ __forceinline__ T bulk(D x) {
+  if constexpr (std::is_same<T, D>::value)
+    return x;
+  else
+    return T(x);
+}
+
 // Interface flux at one point in the face frame (first axis = face normal).
-// WL/WR: conservative values (FP64); DL/DR[d*5+v]: derivative of variable v along face-frame axis d.
-// out: Fn[5], Ft[5], QLn[5], QLt[5], QRn[5], QRt[5].  NOUT = 10 skips the interface values.
+// Each side's state is Q0 + V: Q0L/Q0R[5] the average of the cell the side belongs to (FP64), VL/VR[5]
+// the reconstructed point value relative to it (T); DL/DR[d*5+v]: derivative of variable v along
+// face-frame axis d.  Outputs: Fn[5] = F^n (FP64); out[0..4] = F_t; with IFACE also
+// out[5..9] = Q^l_n - Q0L, out[10..14] = Q^l_t, out[15..19] = Q^r_n - Q0R, out[20..24] = Q^r_t
+// (interface values relative to the own cell's average, which cancels in the closed surface sum of
+// the cell's gradient).  D is double (a counting type in the flop counter).
 //
 // Each Maxwellian (the two sides, then g0) is handled in its own tangentially co-moving frame, where
 // the moment products are sparse; the results are shifted back to the lab before they are summed.
 // Slopes are solved from the density-weighted derivatives directly (b = rho a), so every piece comes
 // out density-weighted without a division.
-template <class T, int NOUT>
-__host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt, const double* WL,
-                                         const T* DL, const double* WR, const T* DR, T* out) {
+template <class T, bool IFACE, class D = double>
+__host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt, const double* Q0L,
+                                                  const T* VL, const T* DL, const double* Q0R,
+                                                  const T* VR, const T* DR, D* Fn, T* out) {
   const T K = T(P.Kdof);
   const T ik3 = T(P.ik3);
-  const double gm1 = P.gamma - 1.0;
-  // primitive variables in FP64
-  double pres[2];
-  Prim<T> pr[2];
-  {
-    const double* Ws[2] = {WL, WR};
+  const D gm1 = D(P.gamma - 1.0);
+  const D kp2 = D(P.Kdof + 2.0);
+  D Ws[2][5];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const double rho = Ws[s][0];
-      const double ir = 1.0 / rho;
-      const double U = Ws[s][1] * ir, V = Ws[s][2] * ir, W = Ws[s][3] * ir;
-      const double p = gm1 * (Ws[s][4] - 0.5 * rho * (U * U + V * V + W * W));
-      pres[s] = p;
-      pr[s].rho = data<T>(rho);
-      pr[s].U = data<T>(U);
-      pr[s].V = data<T>(V);
-      pr[s].W = data<T>(W);
-      pr[s].var = data<T>(p * ir);
-      pr[s].lam = T(0.5) * drcp(pr[s].var);
+  for (int v = 0; v < 5; ++v) {
+    Ws[0][v] = data<D>(Q0L[v]) + bulk<D>(VL[v]);
+    Ws[1][v] = data<D>(Q0R[v]) + bulk<D>(VR[v]);
+  }
+  // FP64: primitives of both sides, and their half-space sums W0 = sum_s rho_s <psi>_s and
+  // SP0 = sum_s rho_s <u psi>_s (side l over u > 0, side r over u < 0), in the lab frame
+  D pres[2], W0[5], SP0[5];
+  Prim<T> pr[2];
+  T u03[2][4];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const D rho = Ws[s][0];
+    const D ir = D(1) / rho;
+    const D U = Ws[s][1] * ir, V = Ws[s][2] * ir, W = Ws[s][3] * ir;
+    const D p = gm1 * (Ws[s][4] - D(0.5) * rho * (U * U + V * V + W * W));
+    const D var = p * ir;
+    pres[s] = p;
+    pr[s].rho = bulk<T>(rho);
+    pr[s].U = bulk<T>(U);
+    pr[s].V = bulk<T>(V);
+    pr[s].W = bulk<T>(W);
+    pr[s].var = bulk<T>(var);
+    pr[s].lam = T(0.5) * drcp(pr[s].var);
+    D pp, pm, tail;
+    normal_split(U, var, pp, pm, tail);
+    const D u0 = s == 0 ? pp : pm;
+    const D u1 = s == 0 ? U * u0 + tail : U * u0 - tail;
+    const D u2 = U * u1 + var * u0;
+    const D u3 = U * u2 + D(2) * var * u1;
+    u03[s][0] = bulk<T>(u0);
+    u03[s][1] = bulk<T>(u1);
+    u03[s][2] = bulk<T>(u2);
+    u03[s][3] = bulk<T>(u3);
+    // <v^2 + w^2 + xi^2> / 2 in the lab
+    const D kr = D(0.5) * (V * V + W * W + kp2 * var);
+    const D w[5] = {rho * u0, rho * u1, rho * V * u0, rho * W * u0, rho * (D(0.5) * u2 + kr * u0)};
+    const D f[5] = {rho * u1, rho * u2, rho * V * u1, rho * W * u1, rho * (D(0.5) * u3 + kr * u1)};
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      W0[v] = s == 0 ? w[v] : W0[v] + w[v];
+      SP0[v] = s == 0 ? f[v] : SP0[v] + f[v];
+    }
+  }
+  // relative pressure jump |p_l - p_r| / (p_l + p_r): the difference in FP64, the ratio in T
+  const T jump = bulk<T>(fabs(pres[0] - pres[1])) * drcp(bulk<T>(pres[0] + pres[1]));
+
+  // interface equilibrium g0: primitives and Euler flux G0 = rho0 <u psi> in FP64; the difference
+  // SP0 - G0 of the two equilibrium fluxes is small where the flow is smooth and goes on in T
+  const D ir0 = D(1) / W0[0];
+  const D U0 = W0[1] * ir0, V0 = W0[2] * ir0, Wv0 = W0[3] * ir0;
+  const D p064 = gm1 * (W0[4] - D(0.5) * W0[0] * (U0 * U0 + V0 * V0 + Wv0 * Wv0));
+  const D G0[5] = {W0[1], W0[1] * U0 + p064, W0[1] * V0, W0[1] * Wv0, U0 * (W0[4] + p064)};
+  T dS[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) dS[v] = bulk<T>(SP0[v] - G0[v]);
+  Prim<T> p0;
+  p0.rho = bulk<T>(W0[0]);
+  p0.U = bulk<T>(U0);
+  p0.V = bulk<T>(V0);
+  p0.W = bulk<T>(Wv0);
+  p0.var = bulk<T>(p064 * ir0);
+  p0.lam = T(0.5) * drcp(p0.var);
+  const T pe = bulk<T>(p064);
+  // the equilibrium parts of the two sides' interface values, relative to QL0 / QR0:
+  // (1 - w) (W0 - Q0) + w (W^s - Q0), w = e^{-dt/tau0}, tau0 = C jump dt (a zero jump gives w = 0)
+  T w = T(0), w1 = T(1), oL[5], oR[5];
+  if constexpr (IFACE) {
+    w = dexp(-drcp(T(P.tau_c) * jump));
+    w1 = T(1) - w;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      oL[v] = w1 * bulk<T>(W0[v] - data<D>(Q0L[v])) + w * VL[v];
+      oR[v] = w1 * bulk<T>(W0[v] - data<D>(Q0R[v])) + w * VR[v];
     }
   }
 
   // lab sums over the two sides, each piece density-weighted on its half space:
-  // W0 = <psi>, dW0[d] = <a_d psi>, SP = {<u psi>, <u (a.u) psi>, <u A psi>, -, <(a.u) psi>, <A psi>}
-  T W0[5], dW0[3][5], SP[6][5];
+  // dW0[d] = <a_d psi>, SP = {-, <u (a.u) psi>, <u A psi>, -, <(a.u) psi>, <A psi>}
+  T dW0[3][5], SP[6][5];
   T eul[2][5];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const Prim<T>& p = pr[s];
-    const T* D = s ? DR : DL;
+    const T* Dd = s ? DR : DL;
     const T V = p.V, W = p.W, kv = T(0.5) * (V * V + W * W);
     FrameMom<T> mh, mf;
     if (s == 0)
-      frame_moments<+1>(p, K, mh);
+      frame_moments<+1>(p, K, mh, u03[0]);
     else
-      frame_moments<-1>(p, K, mh);
+      frame_moments<-1>(p, K, mh, u03[1]);
     frame_moments<0>(p, K, mf);
     SlopeSolver<T> sv;
     sv.init(p, K, ik3);
@@ -298,7 +341,7 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
     T Dp[3][5], b[3][5];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      to_frame(D + 5 * d, V, W, kv, Dp[d]);
+      to_frame(Dd + 5 * d, V, W, kv, Dp[d]);
       sv.solve(Dp[d], b[d]);
     }
     // Euler time derivative of the side: rho E = <(a.u) psi> over the full range, with the lab
@@ -315,10 +358,8 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
       for (int v = 0; v < 5; ++v) RA[v] = -E[v];
       sv.solve(RA, B);
     }
-    // the side's pieces on its half space
-    T w0[5], dw[3][5], s0[5], s1[5], s2[5], s4[5], s5[5];
-    tpsi<0>(mh, p.rho, w0);
-    tpsi<1>(mh, p.rho, s0);
+    // the side's slope pieces on its half space
+    T dw[3][5], s1[5], s2[5], s4[5], s5[5];
 #pragma unroll
     for (int d = 0; d < 3; ++d) tslope<0, true>(mh, b[d], dw[d]);
     {
@@ -339,8 +380,6 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
     for (int v = 0; v < 5; ++v) s4[v] = s4[v] + V * dw[1][v] + W * dw[2][v];
     tslope<0, true>(mh, B, s5);
     if (s == 0) {
-      from_frame<true, true>(w0, V, W, kv, W0);
-      from_frame<true, true>(s0, V, W, kv, SP[0]);
 #pragma unroll
       for (int d = 0; d < 3; ++d) from_frame<true>(dw[d], V, W, kv, dW0[d]);
       from_frame<true>(s1, V, W, kv, SP[1]);
@@ -348,8 +387,6 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
       from_frame<true>(s4, V, W, kv, SP[4]);
       from_frame<true>(s5, V, W, kv, SP[5]);
     } else {
-      from_frame<false, true>(w0, V, W, kv, W0);
-      from_frame<false, true>(s0, V, W, kv, SP[0]);
 #pragma unroll
       for (int d = 0; d < 3; ++d) from_frame<false>(dw[d], V, W, kv, dW0[d]);
       from_frame<false>(s1, V, W, kv, SP[1]);
@@ -357,24 +394,15 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
       from_frame<false>(s4, V, W, kv, SP[4]);
       from_frame<false>(s5, V, W, kv, SP[5]);
     }
-    if constexpr (NOUT > 10) {
+    if constexpr (IFACE) {
       from_frame<true>(E, V, W, kv, eul[s]);
 #pragma unroll
       for (int v = 0; v < 5; ++v) eul[s][v] = -eul[s][v];
     }
   }
 
-  // interface equilibrium g0, in its own tangential frame
-  Prim<T> p0;
-  p0.rho = W0[0];
-  const T ir0 = drcp(W0[0]);
-  p0.U = W0[1] * ir0;
-  p0.V = W0[2] * ir0;
-  p0.W = W0[3] * ir0;
-  const T pe = T(gm1) * (W0[4] - T(0.5) * W0[0] * (p0.U * p0.U + p0.V * p0.V + p0.W * p0.W));
-  p0.var = pe * ir0;
-  p0.lam = T(0.5) * drcp(p0.var);
-  // G = rho0 x {<u psi>, <u (ab.u) psi>, <u Ab psi>, -, <(ab.u) psi>}; <Ab psi> = -<(ab.u) psi>
+  // G = rho0 x {-, <u (ab.u) psi>, <u Ab psi>, -, <(ab.u) psi>}, in g0's tangential frame;
+  // <Ab psi> = -<(ab.u) psi>
   T G[5][5];
   {
     const T V = p0.V, W = p0.W, kv = T(0.5) * (V * V + W * W);
@@ -400,8 +428,7 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
       for (int v = 0; v < 5; ++v) RA[v] = -E[v];
       sv.solve(RA, Bb);
     }
-    T g0[5], g1[5], g2[5];
-    tpsi<1>(m0, p0.rho, g0);
+    T g1[5], g2[5];
     {
       T VW[5];
 #pragma unroll
@@ -412,15 +439,12 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
       tslope<1>(m0, VW, g1);
     }
     tslope<1, true>(m0, Bb, g2);
-    from_frame<true, true>(g0, V, W, kv, G[0]);
     from_frame<true>(g1, V, W, kv, G[1]);
     from_frame<true>(g2, V, W, kv, G[2]);
     from_frame<true>(E, V, W, kv, G[4]);
   }
 
   // collision time (Sec. 4 opening)
-  // relative pressure jump |p_l - p_r| / (p_l + p_r): the difference in FP64, the ratio in T
-  const T jump = data<T>(fabs(pres[0] - pres[1])) * drcp(data<T>(pres[0] + pres[1]));
   const T Dt = T(dt);
   T tau;
   if (P.mu0 > 0.0)
@@ -436,7 +460,6 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
   const T r = tau * iDt;
   const T rq = r * om * (T(3) - e1);
   T cn[6], ct[6];
-  cn[0] = T(1) - rq;
   cn[1] = T(2) * tau * rq + tau * (e1 * e1 - T(2) * e1 - T(1));
   cn[2] = tau * (rq - T(1));
   cn[3] = rq;
@@ -449,44 +472,39 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
   ct[4] = -ct[1];
   ct[5] = T(4) * rom * rom;
 
-  T Fn[5], Ft[5];
+  // F^n = (1 - cn3) G0 + cn3 SP0 + the slope and time-derivative products = G0 (FP64) + dF (T);
+  // F_t = ct0 (G0 - SP0) + ...
+  T dF[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    Fn[v] = cn[0] * G[0][v] + cn[1] * G[1][v] + cn[2] * G[2][v] + cn[3] * SP[0][v] +
-            cn[4] * SP[1][v] + cn[5] * SP[2][v];
-    Ft[v] = ct[0] * (G[0][v] - SP[0][v]) + ct[1] * G[1][v] + ct[2] * G[2][v] + ct[4] * SP[1][v] +
-            ct[5] * SP[2][v];
+    dF[v] = cn[3] * dS[v] + cn[1] * G[1][v] + cn[2] * G[2][v] + cn[4] * SP[1][v] + cn[5] * SP[2][v];
+    out[v] = ct[1] * G[1][v] + ct[2] * G[2][v] + ct[4] * SP[1][v] + ct[5] * SP[2][v] - ct[0] * dS[v];
   }
-  // Q: g0 contributes W0 (<psi>) and (cn1 - cn2) <(ab.u) psi>; the sides their own pieces
+  // Q^n = W0 + qs: g0 contributes W0 (<psi>) and (cn1 - cn2) <(ab.u) psi>; the sides their own pieces
   const T cq = cn[1] - cn[2];
-  T Qn[5];
+  T qs[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) Qn[v] = W0[v] + cq * G[4][v] + cn[4] * SP[4][v] + cn[5] * SP[5][v];
+  for (int v = 0; v < 5; ++v) qs[v] = cq * G[4][v] + cn[4] * SP[4][v] + cn[5] * SP[5][v];
   if (P.mu0 > 0.0 && P.prandtl > 0.0 && P.prandtl != 1.0) {
+    // heat flux of f^n in the g0 frame, q(F) - U0 e(Q) with q(F) = F_E - U0.F_m + |U0|^2/2 F_rho and
+    // e(Q) = Q_E - U0.Q_m + |U0|^2/2 Q_rho; the Euler parts G0 and W0 cancel exactly (q(G0) = U0 e(W0)),
+    // which leaves the same form of dF and qs
     const T k2 = T(0.5) * (p0.U * p0.U + p0.V * p0.V + p0.W * p0.W);
-    const T qf = Fn[4] - (p0.U * Fn[1] + p0.V * Fn[2] + p0.W * Fn[3]) + k2 * Fn[0];
-    const T qq = Qn[4] - (p0.U * Qn[1] + p0.V * Qn[2] + p0.W * Qn[3]) + k2 * Qn[0];
-    Fn[4] += T(1.0 / P.prandtl - 1.0) * (qf - p0.U * qq);
+    const T qf = dF[4] - (p0.U * dF[1] + p0.V * dF[2] + p0.W * dF[3]) + k2 * dF[0];
+    const T qq = qs[4] - (p0.U * qs[1] + p0.V * qs[2] + p0.W * qs[3]) + k2 * qs[0];
+    dF[4] = dF[4] + T(1.0 / P.prandtl - 1.0) * (qf - p0.U * qq);
   }
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    out[v] = Fn[v];
-    out[5 + v] = Ft[v];
-  }
-  if constexpr (NOUT > 10) {
+  for (int v = 0; v < 5; ++v) Fn[v] = G0[v] + bulk<D>(dF[v]);
+  if constexpr (IFACE) {
     const T ctq = ct[1] - ct[2];
-    T Qt[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) Qt[v] = ctq * G[4][v] + ct[4] * SP[4][v] + ct[5] * SP[5][v];
-    // w = e^{-dt/tau0}, tau0 = C jump dt; a zero jump gives w = 0
-    const T w = dexp(-drcp(T(P.tau_c) * jump));
-    const T w1 = T(1) - w;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      out[10 + v] = w1 * Qn[v] + w * data<T>(WL[v]);
-      out[15 + v] = w1 * Qt[v] + w * eul[0][v];
-      out[20 + v] = w1 * Qn[v] + w * data<T>(WR[v]);
-      out[25 + v] = w1 * Qt[v] + w * eul[1][v];
+      const T Qt = ctq * G[4][v] + ct[4] * SP[4][v] + ct[5] * SP[5][v];
+      out[5 + v] = oL[v] + w1 * qs[v];
+      out[10 + v] = w1 * Qt + w * eul[0][v];
+      out[15 + v] = oR[v] + w1 * qs[v];
+      out[20 + v] = w1 * Qt + w * eul[1][v];
     }
   }
 }

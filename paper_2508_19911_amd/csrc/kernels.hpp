@@ -5,7 +5,8 @@
 //            blended) -> coefficient planes C[v*34+m][cell];
 //   k_flux5  one thread per Gauss point of the face on the low side of each cell (one launch per
 //            direction): both sides evaluated from the coefficients of the adjacent cells, the
-//            gas-kinetic flux, the 2x2 Gauss average over 4 lanes -> face planes F[dir*30+n][cell];
+//            gas-kinetic flux, the 2x2 Gauss average over 4 lanes -> face planes: F^n in FP64
+//            Fd[dir*5+v][cell], and F_t and the two sides' interface values in T Fb[dir*25+n][cell];
 //   k_update5 one thread per cell: L, dL/dt and the Gauss-theorem sums of the interface values
 //            from the six faces, then the two-stage update (Sec. 3.4).
 // GKS-2nd (Sec. 3.3): k_slopes2 (P^1 + Venkatakrishnan), k_flux2 (face midpoints), k_update2.
@@ -268,16 +269,20 @@ constexpr int FLUX_BLK = 4 * FLUX_FACES;
 
 template <class T>
 struct FluxShared {
-  double W[FLUX_FACES][4][10];   // [face][point][side * 5 + face-frame variable]: conservative value
+  double Q0[FLUX_FACES][10];     // [face][side * 5 + face-frame variable]: the side's cell average
+  T V[FLUX_FACES][4][10];        // [face][point][side * 5 + variable]: point value minus the average
   T D[FLUX_FACES][4][10][3];     // face-frame derivatives, physical units
 };
 
-// FP64 asks for two waves per SIMD: it then spills a few registers to scratch but runs 1.12x faster
-// than at one wave with every value in registers (measured at 128^3).
+// Occupancy (measured at 128^3): the FP32 form asks for three waves per SIMD, which spills about a
+// dozen registers held across the slope products (0.651 ms per launch against 0.688 at two waves
+// without spills); FP64 runs at one wave with every value in registers (1.40 ms per launch against
+// 1.47 at two waves, where 55 registers spill).
 template <class T, int DIR>
-__global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 2 : 1) void k_flux5(Grid g, const double* __restrict__ Q,
-                                                    const T* __restrict__ C, T* __restrict__ F,
-                                                    FluxParams fp, const double* __restrict__ ctl) {
+__global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 1 : 3) void k_flux5(Grid g, const double* __restrict__ Q,
+                                                    const T* __restrict__ C, double* __restrict__ Fd,
+                                                    T* __restrict__ Fb, FluxParams fp,
+                                                    const double* __restrict__ ctl) {
   __shared__ FluxShared<T> sh;
   if (ctl[1] != 0.0) return;  // the step was stopped (see k_step_control)
   const double dt = ctl[0];
@@ -317,40 +322,53 @@ __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 2 : 1) void k_flux5(Grid
       T val[4], der[4][3];
       eval_face<FP>(a, side ? T(-1) : T(1), val, der);
       const double q0 = ld(Q + vg * N, (uint32_t)src);
+      sh.Q0[fl][vs] = q0;
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        sh.W[fl][p][vs] = q0 + double(val[p]);
+        sh.V[fl][p][vs] = val[p];
 #pragma unroll
         for (int dd = 0; dd < 3; ++dd) sh.D[fl][p][vs][dd] = der[p][perm(DIR, dd)] * T(g.ih[perm(DIR, dd)]);
       }
     }
   }
   __syncthreads();
-  double WL[5], WR[5];
-  T DL[15], DR[15];
+  double QL0[5], QR0[5];
+  T VL[5], VR[5], DL[15], DR[15];
 #pragma unroll
   for (int vf = 0; vf < 5; ++vf) {
-    WL[vf] = sh.W[fl][kgp][vf];
-    WR[vf] = sh.W[fl][kgp][5 + vf];
+    VL[vf] = sh.V[fl][kgp][vf];
+    VR[vf] = sh.V[fl][kgp][5 + vf];
+    QL0[vf] = sh.Q0[fl][vf];
+    QR0[vf] = sh.Q0[fl][5 + vf];
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd) {
       DL[dd * 5 + vf] = sh.D[fl][kgp][vf][dd];
       DR[dd * 5 + vf] = sh.D[fl][kgp][5 + vf][dd];
     }
   }
-  T out[30];
-  gks_flux<T, 30>(fp, dt, WL, DL, WR, DR, out);
+  double Fn[5];
+  T out[25];
+  gks_flux<T, true>(fp, dt, QL0, VL, DL, QR0, VR, DR, Fn, out);
   // 2x2 Gauss average over the four lanes of the face
 #pragma unroll
-  for (int n = 0; n < 30; ++n) out[n] = T(0.25) * quad_sum(out[n]);
+  for (int n = 0; n < 5; ++n) Fn[n] = 0.25 * quad_sum(Fn[n]);
+#pragma unroll
+  for (int n = 0; n < 25; ++n) out[n] = T(0.25) * quad_sum(out[n]);
   if (active) {
+    // output n = 5 * block + face-frame variable: block 0 is F^n (FP64 planes), blocks 1..5 are
+    // F_t, Q^l_n - Q0^l, Q^l_t, Q^r_n - Q0^r, Q^r_t (T planes); each lane stores a quarter
 #pragma unroll
     for (int blk = 0; blk < 6; ++blk)
 #pragma unroll
       for (int vf = 0; vf < 5; ++vf) {
         const int vg = (vf >= 1 && vf <= 3) ? 1 + perm(DIR, vf - 1) : vf;
         const int n = blk * 5 + vf;
-        if ((n & 3) == kgp) st(F + (DIR * 30 + blk * 5 + vg) * N, (uint32_t)cell, out[n]);
+        if ((n & 3) == kgp) {
+          if (blk == 0)
+            st(Fd + (DIR * 5 + vg) * N, (uint32_t)cell, Fn[vf]);
+          else
+            st(Fb + (DIR * 25 + (blk - 1) * 5 + vg) * N, (uint32_t)cell, out[n - 5]);
+        }
       }
   }
 }
@@ -376,18 +394,26 @@ __global__ __launch_bounds__(64) void k_point_flux(long long n, const double* __
   const long long p = (long long)blockIdx.x * 64 + threadIdx.x;
   if (p >= n) return;
   double WL[5], WR[5];
-  T DL[15], DR[15];
+  T zero[5], DL[15], DR[15];
   for (int v = 0; v < 5; ++v) {
     WL[v] = wl[p * 20 + v];
     WR[v] = wr[p * 20 + v];
+    zero[v] = T(0);
   }
   for (int q = 0; q < 15; ++q) {
     DL[q] = T(wl[p * 20 + 5 + q]);
     DR[q] = T(wr[p * 20 + 5 + q]);
   }
-  T o[30];
-  gks_flux<T, 30>(fp, dt, WL, DL, WR, DR, o);
-  for (int q = 0; q < 30; ++q) out[p * 30 + q] = double(o[q]);
+  double Fn[5];
+  T o[25];
+  gks_flux<T, true>(fp, dt, WL, zero, DL, WR, zero, DR, Fn, o);
+  for (int q = 0; q < 5; ++q) out[p * 30 + q] = Fn[q];
+  for (int q = 0; q < 25; ++q) out[p * 30 + 5 + q] = double(o[q]);
+  // interface values relative to the states given: add them back
+  for (int v = 0; v < 5; ++v) {
+    out[p * 30 + 10 + v] += WL[v];
+    out[p * 30 + 20 + v] += WR[v];
+  }
 }
 
 // ============================================================================ CGKS-5th update
@@ -401,7 +427,8 @@ struct Stage5Out {
 };
 
 template <class T, int STAGE>  // 0 debug, 1 first stage, 2 second stage
-__global__ __launch_bounds__(BLK) void k_update5(Grid g, const T* __restrict__ F,
+__global__ __launch_bounds__(BLK) void k_update5(Grid g, const double* __restrict__ Fd,
+                                                 const T* __restrict__ Fb,
                                                  const double* __restrict__ Qn, Stage5Out o,
                                                  const double* __restrict__ ctl) {
   const int cell = blockIdx.x * BLK + threadIdx.x;
@@ -424,13 +451,15 @@ __global__ __launch_bounds__(BLK) void k_update5(Grid g, const T* __restrict__ F
     Lt[v] = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const T* Fd = F + (long long)(d * 30) * N;
-      L[v] -= (double(Fd[v * N + cp[d]]) - double(Fd[v * N + cell])) * g.ih[d];
-      Lt[v] -= (double(Fd[(5 + v) * N + cp[d]]) - double(Fd[(5 + v) * N + cell])) * g.ih[d];
-      // this cell is the left cell of its + face and the right cell of its - face
+      const double* Fn = Fd + (long long)(d * 5) * N;
+      const T* Fo = Fb + (long long)(d * 25) * N;
+      L[v] -= (Fn[v * N + cp[d]] - Fn[v * N + cell]) * g.ih[d];
+      Lt[v] -= (double(Fo[v * N + cp[d]]) - double(Fo[v * N + cell])) * g.ih[d];
+      // this cell is the left cell of its + face and the right cell of its - face; both interface
+      // values are stored relative to this cell's average, which cancels in the closed surface sum
       if constexpr (STAGE != 2)
-        sn[d][v] = (double(Fd[(10 + v) * N + cp[d]]) - double(Fd[(20 + v) * N + cell])) * g.ih[d];
-      st[d][v] = (double(Fd[(15 + v) * N + cp[d]]) - double(Fd[(25 + v) * N + cell])) * g.ih[d];
+        sn[d][v] = (double(Fo[(5 + v) * N + cp[d]]) - double(Fo[(15 + v) * N + cell])) * g.ih[d];
+      st[d][v] = (double(Fo[(10 + v) * N + cp[d]]) - double(Fo[(20 + v) * N + cell])) * g.ih[d];
     }
   }
   double q[5];
@@ -527,8 +556,9 @@ __global__ __launch_bounds__(BLK) void k_slopes2(Grid g, const double* __restric
 
 template <class T, int DIR>
 __global__ __launch_bounds__(BLK) void k_flux2(Grid g, const double* __restrict__ Q,
-                                               const T* __restrict__ S, T* __restrict__ F,
-                                               FluxParams fp, const double* __restrict__ ctl) {
+                                               const T* __restrict__ S, double* __restrict__ Fd,
+                                               T* __restrict__ Fb, FluxParams fp,
+                                               const double* __restrict__ ctl) {
   const int cell = blockIdx.x * BLK + threadIdx.x;
   if (cell >= g.N || ctl[1] != 0.0) return;
   const double dt = ctl[0];
@@ -536,14 +566,16 @@ __global__ __launch_bounds__(BLK) void k_flux2(Grid g, const double* __restrict_
   cell_ijk(g, cell, i, j, k);
   const int left = neighbour_m<DIR>(g, cell, i, j, k);
   const long long N = g.N;
-  double WL[5], WR[5];
-  T DL[15], DR[15];
+  double QL[5], QR[5];
+  T VL[5], VR[5], DL[15], DR[15];
 #pragma unroll
   for (int vf = 0; vf < 5; ++vf) {
     const int vg = (vf >= 1 && vf <= 3) ? 1 + perm(DIR, vf - 1) : vf;
     const T* Sv = S + (long long)(vg * 3) * N;
-    WL[vf] = Q[vg * N + left] + 0.5 * double(Sv[DIR * N + left]);
-    WR[vf] = Q[vg * N + cell] - 0.5 * double(Sv[DIR * N + cell]);
+    QL[vf] = Q[vg * N + left];
+    QR[vf] = Q[vg * N + cell];
+    VL[vf] = T(0.5) * Sv[DIR * N + left];
+    VR[vf] = T(-0.5) * Sv[DIR * N + cell];
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd) {
       const int e = perm(DIR, dd);
@@ -551,19 +583,20 @@ __global__ __launch_bounds__(BLK) void k_flux2(Grid g, const double* __restrict_
       DR[dd * 5 + vf] = Sv[e * N + cell] * T(g.ih[e]);
     }
   }
-  T out[10];
-  gks_flux<T, 10>(fp, dt, WL, DL, WR, DR, out);
+  double Fn[5];
+  T out[5];
+  gks_flux<T, false>(fp, dt, QL, VL, DL, QR, VR, DR, Fn, out);
 #pragma unroll
-  for (int blk = 0; blk < 2; ++blk)
-#pragma unroll
-    for (int vf = 0; vf < 5; ++vf) {
-      const int vg = (vf >= 1 && vf <= 3) ? 1 + perm(DIR, vf - 1) : vf;
-      F[(DIR * 10 + blk * 5 + vg) * N + cell] = out[blk * 5 + vf];
-    }
+  for (int vf = 0; vf < 5; ++vf) {
+    const int vg = (vf >= 1 && vf <= 3) ? 1 + perm(DIR, vf - 1) : vf;
+    Fd[(DIR * 5 + vg) * N + cell] = Fn[vf];
+    Fb[(DIR * 5 + vg) * N + cell] = out[vf];
+  }
 }
 
 template <class T, int DEBUG>
-__global__ __launch_bounds__(BLK) void k_update2(Grid g, const T* __restrict__ F, double* Q,
+__global__ __launch_bounds__(BLK) void k_update2(Grid g, const double* __restrict__ Fd,
+                                                 const T* __restrict__ Fb, double* Q,
                                                  double* Lout, double* Ltout, const double* __restrict__ ctl) {
   const int cell = blockIdx.x * BLK + threadIdx.x;
   if (cell >= g.N || ctl[1] != 0.0) return;
@@ -581,9 +614,10 @@ __global__ __launch_bounds__(BLK) void k_update2(Grid g, const T* __restrict__ F
     Lt[v] = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const T* Fd = F + (long long)(d * 10) * N;
-      L[v] -= (double(Fd[v * N + cp[d]]) - double(Fd[v * N + cell])) * g.ih[d];
-      Lt[v] -= (double(Fd[(5 + v) * N + cp[d]]) - double(Fd[(5 + v) * N + cell])) * g.ih[d];
+      const double* Fn = Fd + (long long)(d * 5) * N;
+      const T* Ft = Fb + (long long)(d * 5) * N;
+      L[v] -= (Fn[v * N + cp[d]] - Fn[v * N + cell]) * g.ih[d];
+      Lt[v] -= (double(Ft[v * N + cp[d]]) - double(Ft[v * N + cell])) * g.ih[d];
     }
     if constexpr (!DEBUG) q[v] = Q[v * N + cell];
   }

@@ -234,13 +234,37 @@ def tgv_state(case: Case):
     return cell_average(case, fn), gauss_gradient(case, fn)
 
 
+def _counter_uniform(seed: int, i: np.ndarray) -> np.ndarray:
+    """Uniforms in (0, 1) of a counter-based generator: the SplitMix64 output function (Steele, Lea and
+    Flood, OOPSLA 2014) of seed + (i + 1) * 0x9e3779b97f4a7c15 (mod 2^64), top 53 bits plus 1/2."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (i + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return ((z >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+
+
+def counter_normals(seed: int, start: int, count: int) -> np.ndarray:
+    """Standard normals j = start .. start + count - 1: the Box-Muller pair of the uniforms 2m, 2m+1
+    (m = j // 2), cos for even j and sin for odd j."""
+    j = np.arange(start, start + count, dtype=np.uint64)
+    m = j >> np.uint64(1)
+    u1 = _counter_uniform(seed, np.uint64(2) * m)
+    u2 = _counter_uniform(seed, np.uint64(2) * m + np.uint64(1))
+    r = np.sqrt(-2.0 * np.log(u1))
+    th = 2.0 * np.pi * u2
+    return np.where((j & np.uint64(1)) == 1, r * np.sin(th), r * np.cos(th))
+
+
 def hit_state(case: Case):
     """Seeded random solenoidal velocity with E(k) ~ k^4 exp(-2 k^2/k0^2), 1 <= |k| <= n/2, exact
     Fourier cell averages and cell-averaged gradients, one global scale so <|u|^2> = 3; rho = 1,
-    uniform p; energy from the cell-averaged velocity."""
+    uniform p; energy from the cell-averaged velocity.  The white noise of component c at cell m
+    (x fastest) is counter_normals(seed) number c N + m."""
     n = case.nx
     assert case.ny == n and case.nz == n
-    rng = np.random.Generator(np.random.PCG64(case.seed))
+    N = n ** 3
     k0 = 8.0
     k1 = np.fft.fftfreq(n, d=1.0 / n)
     KZ, KY, KX = np.meshgrid(k1, k1, k1, indexing="ij")
@@ -249,8 +273,8 @@ def hit_state(case: Case):
     amp = np.where((Km >= 1.0) & (Km <= n / 2), Km ** 2 * np.exp(-(Km / k0) ** 2), 0.0)
     amp = np.where(Km > 0, amp / np.maximum(Km, 1.0), 0.0)  # |u_k| ~ sqrt(E(k) / k^2)
     uh = []
-    for _ in range(3):
-        noise = rng.standard_normal((n, n, n))
+    for c in range(3):
+        noise = counter_normals(case.seed, c * N, N).reshape(n, n, n)
         uh.append(np.fft.fftn(noise) * amp)
     kv = (KX, KY, KZ)
     kdu = sum(kv[i] * uh[i] for i in range(3))

@@ -15,22 +15,30 @@ extern "C" {
 void host_point_flux(int precision, double gamma, double mu0, double tref, double prandtl, double tau_eps,
                      double tau_c, double dt, const double* wl, const double* wr, double* out) {
   const FluxParams fp = make_flux_params(gamma, mu0, tref, prandtl, tau_eps, tau_c);
+  // each side's state is its cell average wl / wr plus a zero point value; the interface values
+  // come back relative to it and are returned absolute
   if (precision == 0) {
-    double dl[15], dr[15], o[30];
+    const double zero[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double dl[15], dr[15], o[25];
     for (int i = 0; i < 15; ++i) {
       dl[i] = wl[5 + i];
       dr[i] = wr[5 + i];
     }
-    gks_flux<double, 30>(fp, dt, wl, dl, wr, dr, o);
-    for (int i = 0; i < 30; ++i) out[i] = o[i];
+    gks_flux<double, true>(fp, dt, wl, zero, dl, wr, zero, dr, out, o);
+    for (int i = 0; i < 25; ++i) out[5 + i] = o[i];
   } else {
-    float dl[15], dr[15], o[30];
+    const float zero[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    float dl[15], dr[15], o[25];
     for (int i = 0; i < 15; ++i) {
       dl[i] = (float)wl[5 + i];
       dr[i] = (float)wr[5 + i];
     }
-    gks_flux<float, 30>(fp, dt, wl, dl, wr, dr, o);
-    for (int i = 0; i < 30; ++i) out[i] = o[i];
+    gks_flux<float, true>(fp, dt, wl, zero, dl, wr, zero, dr, out, o);
+    for (int i = 0; i < 25; ++i) out[5 + i] = o[i];
+  }
+  for (int v = 0; v < 5; ++v) {
+    out[10 + v] += wl[v];
+    out[20 + v] += wr[v];
   }
 }
 

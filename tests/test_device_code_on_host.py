@@ -103,3 +103,28 @@ def test_parity_class_face_evaluation_matches_tables(lib, e):
             assert abs(val[g] - PV[f][g] @ a) <= 1e-13 * np.abs(a).sum()
             for x in range(3):
                 assert abs(der[g * 3 + x] - PD[f][g][x] @ a) <= 1e-13 * np.abs(a).sum()
+
+
+def test_fp32_form_keeps_the_pressure_scale_in_fp64(lib):
+    """FP32-bulk flux at Ma 0.1 (p ~ 71 against O(1) velocity variations): the pressure-sized parts
+    (W0, its Euler flux, the half-space sums, the assembly of F^n and of the interface values) are
+    FP64, so F^n and the interface values match the FP64 oracle far below FP32 rounding of p
+    (6e-8 * 71 = 4e-6).  With those parts in FP32 the errors were 1e-6 (mass) to 2e-4 (energy)."""
+    case = inputs.tgv_case(8)
+    P = oracle.params_from_config(case)
+    rng = np.random.default_rng(3)
+    p0 = 1.0 / (GAMMA * 0.01)
+    err = np.zeros(30)
+    for _ in range(40):
+        base = cons(1 + 0.05 * rng.normal(), rng.normal(), rng.normal(), rng.normal(), p0 * (1 + 0.01 * rng.normal()))
+        d = rng.normal(scale=1e-6, size=5) * np.array([1, 1, 1, 1, 100])
+        wl = np.concatenate([base + d, rng.normal(scale=1e-3, size=15)])
+        wr = np.concatenate([base - d, rng.normal(scale=1e-3, size=15)])
+        ref = oracle.point_flux(P, 1e-3, wl, wr)
+        o = np.zeros(30)
+        lib.host_point_flux(1, GAMMA, case.mu0, case.sutherland_tref, case.prandtl, case.tau_eps, case.tau_c,
+                            1e-3, _p(wl), _p(wr), _p(o))
+        err = np.maximum(err, np.abs(o - ref))
+    # F^n and the two sides' interface values (absolute; |F| and |Q| up to ~250)
+    assert err[0:5].max() <= 1e-9, err[0:5]
+    assert err[10:15].max() <= 1e-9 and err[20:25].max() <= 1e-9, (err[10:15], err[20:25])

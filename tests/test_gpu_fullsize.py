@@ -97,7 +97,7 @@ def test_hit256_stage_at_sampled_cells(precision):
     from paper_2508_19911_amd import cgks
     case = inputs.hit_case(256).with_(recon=cgks.RECON_NONLINEAR)
     s = cgks.Solver(case, precision=precision)
-    s.set_state(*inputs.hit_state(case))
+    s.set_ic(cgks.IC_HIT, [case.ma], seed=case.seed)
     s.step(1, case.cfl)
     dt = s.compute_dt(case.cfl)
     compare_sampled(case, s, dt, precision, seed=1)

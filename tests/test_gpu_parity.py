@@ -1,10 +1,10 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
 
-FP64 bar: <= 1e-12 relative, measured against each quantity's natural scale -- max|Q| for the
-state, max|Q| (|U|+c)/h for L, max|Q| (|U|+c)^2/h^2 for dL/dt, max|Q|/h for the gradient sums (the
-rounding floor of any FP64 implementation is ~1e-16 of these) -- and field by field in L2 with a floor
-at 1e-6 of the largest field (so identically-zero fields, rho W in 2-D, compare roundoff at the
-largest field's scale).  Grids span several blocks with ragged tails.  The FP32-bulk form is checked
+FP64 bar: <= 1e-12 relative, element by element against the natural scale of each conservative
+field (rho, the momenta and rho E separately; see scales(): the size of the field's state, flux and
+their rates, whose 1e-16 is the rounding floor of any FP64 implementation), and field by field in L2
+with a floor at 1e-6 of the largest field (so identically-zero fields, rho W in 2-D, compare roundoff
+at the largest field's scale).  Grids span several blocks with ragged tails.  The FP32-bulk form is checked
 against the same oracle with a bar of O(100) float roundings at the same scales.
 """
 import math
@@ -24,20 +24,30 @@ def cg():
 
 
 def scales(case, q):
-    """Natural scales of the stage outputs: the rounding floor of any FP64 implementation is ~1e-16
-    of these.  L ~ Q (|U| + c) / h, dL/dt ~ L (|U| + c) / h, interface sums ~ Q / h and ~ Q (|U|+c)/h^2."""
+    """Natural scales of the stage outputs, per conservative field (rho; the three momenta; rho E),
+    from the state q: with a = |U|_max + c the signal speed of a cell,
+      Q:   rho, rho a (a momentum's interface values and half-space sums carry rho sqrt(p/rho)), rho E;
+      L:   the size of the field's flux over h: rho a, rho a^2 (the pressure), (rho E + p) a;
+      Lt:  L a / h;  sqn: Q / h;  sqt: Q a / h^2.
+    The rounding floor of any FP64 implementation is ~1e-16 of these.  Each is a vector of 5 (one
+    per field); a row r of a compared array belongs to field r mod 5."""
     rho = q[0]; U = q[1:4] / rho
     p = (case.gamma - 1) * (q[4] - 0.5 * rho * (U ** 2).sum(0))
-    vmax = float((np.abs(U).max(0) + np.sqrt(case.gamma * p / rho)).max())
+    a = np.abs(U).max(0) + np.sqrt(case.gamma * p / rho)
     h = min(case.h)
-    qmax = float(np.abs(q).max())
-    return {"L": qmax * vmax / h, "Lt": qmax * vmax ** 2 / h ** 2, "sqn": qmax / h, "sqt": qmax * vmax / h ** 2,
-            "Q": qmax}
+    sq = np.array([rho.max()] + [(rho * a).max()] * 3 + [np.abs(q[4]).max()])
+    sf = np.array([(rho * a).max()] + [(rho * a * a).max()] * 3 + [((np.abs(q[4]) + p) * a).max()])
+    vmax = float(a.max())
+    return {"L": sf / h, "Lt": sf * vmax / h ** 2, "sqn": sq / h, "sqt": sq * vmax / h ** 2, "Q": sq}
 
 
 def scaled_err(a, b, scale):
-    """max over elements of |a - b| / scale (scale: the quantity's natural magnitude)"""
-    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / scale)
+    """max over elements of |a - b| / scale, element by element against the scale of its own
+    conservative field (arrays are [rows][cells], row r of field r mod 5; scale: 5 values)"""
+    a, b = np.asarray(a), np.asarray(b)
+    rows = a.shape[0]
+    sc = np.asarray(scale, dtype=float)[np.arange(rows) % 5].reshape((rows,) + (1,) * (a.ndim - 1))
+    return float((np.abs(a - b) / sc).max())
 
 
 def field_err(a, b):
@@ -214,6 +224,17 @@ def test_device_initial_condition_matches_inputs():
     qg, gg, _, _ = ss.get_state()
     assert np.abs(qg - qs).max() <= 1e-12 * np.abs(qs).max()
     assert np.abs(gg - gs).max() <= 1e-11 * max(np.abs(gs).max(), 1.0)
+    ch = inputs.hit_case(16, ma_t=1.0, seed=77)
+    qh, gh = inputs.hit_state(ch)
+    for prec in (0, 1):
+        sh = cg().Solver(ch, precision=prec)
+        sh.set_ic(cg().IC_HIT, [ch.ma, 8.0], seed=ch.seed)
+        qg, gg, t, step = sh.get_state()
+        assert t == 0.0 and step == 0
+        assert np.abs(qg - qh).max() <= 1e-12 * np.abs(qh).max()
+        # FP32-bulk keeps the gradients in float
+        assert np.abs(gg - gh).max() <= (1e-12 if prec == 0 else 1e-6) * np.abs(gh).max()
+        sh.close()
     cv = inputs.vortex_case(16)
     qv, gv = inputs.vortex_state(cv)
     sv = cg().Solver(cv)
@@ -427,3 +448,38 @@ def test_tgv32_twenty_steps(precision, tgv32_oracle_20_steps):
         per_field = [rel(qg[v], qo[v]) for v in range(5)]
         print("FP32-bulk after 20 steps, relative L2 per field:", np.array2string(np.array(per_field), precision=2))
         assert max(e_rho, e_E, e_m) <= 1e-5, (e_rho, e_E, e_m)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_supersonic_tgv_geno_steps(precision):
+    """The supersonic Taylor-Green vortex (Ma 2, Re 1600, Pr 0.7, Sutherland; Sec. 4.2) on 16^3 with
+    GENO everywhere: the device runs to t = 3, where shocklets have formed and the blend departs from
+    P^4 in most cells; from that state 8 more steps against the oracle.  FP64 at the FP64 bars per field;
+    the FP32-bulk form within 1e-6 per field (L2)."""
+    cgks = cg()
+    case = inputs.tgv_case(16, ma=2.0, supersonic=True).with_(recon=1)
+    s = cgks.Solver(case, precision=precision)
+    s.set_ic(cgks.IC_TGV_SUPERSONIC, [2.0])
+    _, done, t = s.step(10 ** 6, case.cfl, t_stop=3.0)
+    assert abs(t - 3.0) <= 1e-12 and done > 20
+    assert s.labels(0.01).mean() > 0.3  # the nonlinear blend is active
+    q, g, _, _ = s.get_state()
+    o = oracle.Oracle(oracle.params_from_config(case))
+    o.set_state(q, g)
+    rc, done_o, t_o = o.step(8, case.cfl)
+    assert rc == 0 and done_o == 8
+    _, done_g, t_g = s.step(8, case.cfl)
+    # the FP32-bulk state differs from the oracle's by float rounding, and so do its time steps
+    assert done_g == 8 and abs((t_g - 3.0) - t_o) <= (1e-12 if precision == 0 else 1e-7 * t_o)
+    qo, go, _, _ = o.get_state()
+    qg, gg, _, _ = s.get_state()
+    s.close()
+    if precision == 0:
+        sc = scales(case, q)
+        assert field_err(qg, qo) <= 1e-12 * 8
+        assert scaled_err(qg, qo, sc["Q"]) <= 1e-12 * 8
+        assert scaled_err(gg, go, sc["sqn"]) <= 1e-12 * 8
+    else:
+        rel = [float(np.linalg.norm(qg[v] - qo[v]) / np.linalg.norm(qo[v] - qo[v].mean() + 1e-300))
+               for v in range(5)]
+        assert max(rel) <= 1e-6, rel

@@ -111,7 +111,7 @@ def test_null_context_is_rejected_without_device_work():
     assert lib.cgks_compute_dt(z, 0.5, ctypes.byref(d)) == -1
     assert lib.cgks_step_fixed(z, 1, 0.1) == -1
     assert lib.cgks_stage(z, 0.1, None, None, None, None) == -1
-    assert lib.cgks_set_ic(z, 1, None, 0) == -1
+    assert lib.cgks_set_ic(z, 1, None, 0, 0) == -1
     assert lib.cgks_get_flags(z, None) == -1
     assert lib.cgks_diagnostics_quad(z, 1.0, 1.0, None) == -1
     assert lib.cgks_timing_enable(z, 1) == -1
@@ -136,3 +136,45 @@ def test_reflection_orbits_reproduce_the_operator():
     assert back == R
     assert sum(1 for row in RS for v in row if v != 0) == 216
     assert sum(1 for row in R for v in row if v != 0) == 678
+
+
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_host_turbulence_field_matches_inputs(n):
+    """cgks_ic_host (C++ in the library: counter-based normals, radix-2 FFTs) against inputs.hit_state
+    (numpy FFTs) on the same seed: the same field to rounding.  A host computation; no GPU."""
+    from paper_2508_19911_amd import cgks, inputs
+    case = inputs.hit_case(n, ma_t=0.5, seed=20250827 + n)
+    q, g = cgks.ic_host(case, cgks.IC_HIT, [case.ma, 8.0], case.seed)
+    qp, gp = inputs.hit_state(case)
+    assert np.abs(q - qp).max() <= 1e-12 * np.abs(qp).max()
+    assert np.abs(g - gp).max() <= 1e-12 * np.abs(gp).max()
+    # the field itself: zero mean velocity, u_rms = 1 per component on average, divergence-free
+    # cell-averaged gradients (to rounding), uniform density and pressure
+    u = q[1:4] / q[0]
+    assert np.abs(u.mean(axis=1)).max() <= 1e-12
+    assert abs((u ** 2).sum(0).mean() - 3.0) <= 1e-12
+    div = g[1] + g[7] + g[13]
+    assert np.abs(div).max() <= 1e-10 * np.abs(g[1]).max()
+    assert np.all(q[0] == 1.0)
+    # another seed gives another field
+    q2, _ = cgks.ic_host(case, cgks.IC_HIT, [case.ma], case.seed + 1)
+    assert np.abs(q2[1] - q[1]).max() > 0.1
+
+
+def test_host_turbulence_field_rejects_bad_grids():
+    from paper_2508_19911_amd import cgks, inputs
+    lib = cgks.load()
+    q = np.zeros((5, 24 ** 3)); g = np.zeros((15, 24 ** 3))
+    prm = np.array([0.5])
+    P = ctypes.c_void_p
+    for case in (inputs.hit_case(24), inputs.hit_case(16).with_(nz=8), inputs.hit_case(16).with_(lz=1.0)):
+        p = cgks.params_from_case(case)
+        assert lib.cgks_ic_host(ctypes.byref(p), cgks.IC_HIT, prm.ctypes.data_as(P), 1, 1,
+                                q.ctypes.data_as(P), g.ctypes.data_as(P)) == -1
+    p = cgks.params_from_case(inputs.hit_case(16))
+    for kind in (cgks.IC_TGV, cgks.IC_VORTEX2D, 7):
+        assert lib.cgks_ic_host(ctypes.byref(p), kind, prm.ctypes.data_as(P), 1, 1,
+                                q.ctypes.data_as(P), g.ctypes.data_as(P)) == -1
+    bad = np.array([0.0])
+    assert lib.cgks_ic_host(ctypes.byref(p), cgks.IC_HIT, bad.ctypes.data_as(P), 1, 1,
+                            q.ctypes.data_as(P), g.ctypes.data_as(P)) == -1
