@@ -1,9 +1,9 @@
 """Benchmark of the CGKS-5th stage sweep on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--grid 128]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--grid 256]
 
-Workload: Taylor-Green vortex, Re 1600, Ma 0.1, Pr 0.72, Sutherland, periodic [0, 2pi]^3 at 128^3
-(the configuration the metric is quoted on), initial condition evaluated on the device.  A step is
+Workload: Taylor-Green vortex, Re 1600, Ma 0.1, Pr 0.72, Sutherland, periodic [0, 2pi]^3 at 256^3
+(the grid the equal-error target is stated on), initial condition evaluated on the device.  A step is
 one CGKS-5th time step: the CFL/viscous time-step reduction and the two stages (reconstruction,
 gas-kinetic flux at the face Gauss points, update of averages and gradients).
 
@@ -12,6 +12,9 @@ Metric: Mcell-stage updates/s = cells x 2 stages x K / timed seconds, for
     flags a cell), or FP32-bulk GENO everywhere when no trained indicator is present;
   * FP64 plain (GENO everywhere), measured beside it; the line reports the speedup and the relative
     L2 difference of the two velocity fields after the same steps;
+  * "at equal L2 error": the record of paper_2508_19911_amd/equal_l2.py (results/tgv_equal_l2.json),
+    |u_FP32 - u_FP64| over the FP64 scheme's own error at t = 2.5 per field, attached with the kernel
+    digest it was measured on (marked stale when the kernels changed since);
   * with a trained indicator, FP32-bulk GENO everywhere as context (the form without the switch) and
     the flagged fraction of the learned run.
 The roofline object is for the face-flux kernel (the dominant one): algorithmic flops per launch
@@ -19,7 +22,7 @@ The roofline object is for the face-flux kernel (the dominant one): algorithmic 
 on the library's stream during the timed region (only the flux launches carry events there).
 kernels_ms is a per-class breakdown from as many further steps after the timed region, with every
 launch between events.  cpu_baseline times the FP64 oracle on host cores over a bounded sample of
-the same flow.
+the same flow: one step on all cores, and one step of a smaller grid on one core.
 """
 from __future__ import annotations
 
@@ -121,8 +124,7 @@ def copy_calibration(nbytes=1 << 30):
     torch.cuda.empty_cache()
 
 
-def cpu_baseline(n=56):
-    """The FP64 oracle (OpenMP over the host's cores) on one CGKS-5th GENO step of the same flow at n^3."""
+def _oracle_step_rate(n):
     import oracle
     from paper_2508_19911_amd import inputs
 
@@ -133,9 +135,46 @@ def cpu_baseline(n=56):
     t0 = time.perf_counter()
     rc, done, _ = o.step(1, case.cfl)
     dt = time.perf_counter() - t0
+    return case.N * 2 * done / dt / 1e6, dt
+
+
+def cpu_baseline(n=56, n1=24):
+    """The FP64 oracle on one CGKS-5th GENO step of the same flow: at n^3 with OpenMP over the host's
+    cores, and at n1^3 on one core."""
+    import ctypes
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": case.N * 2 * done / dt / 1e6, "unit": "Mcell-stage/s", "cores": cores, "kind": "oracle",
-            "sample": f"TGV Re1600 Ma0.1 {n}^3, 1 CGKS-5th GENO FP64 step (2 stages), {dt:.1f} s"}
+    rate, dt = _oracle_step_rate(n)
+    out = {"value": rate, "unit": "Mcell-stage/s", "cores": cores, "kind": "oracle",
+           "sample": f"TGV Re1600 Ma0.1 {n}^3, 1 CGKS-5th GENO FP64 step (2 stages), {dt:.1f} s"}
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(1)
+        r1, d1 = _oracle_step_rate(n1)
+        gomp.omp_set_num_threads(cores)
+        out["single_core"] = {"value": r1, "cores": 1,
+                              "sample": f"TGV {n1}^3, 1 CGKS-5th GENO FP64 step, {d1:.1f} s"}
+    except OSError:
+        pass
+    return out
+
+
+def equal_l2_record(n):
+    """The equal-L2 record of paper_2508_19911_amd/equal_l2.py for grid n, if one was written."""
+    path = os.path.join(ROOT, "results", "tgv_equal_l2.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    g = rec.get("grids", {}).get(str(n))
+    if g is None:
+        return None
+    from paper_2508_19911_amd import equal_l2
+    return {"t": rec["t"], "fields": rec["fields"], "variant": rec["variant"],
+            "ratio_fp32_minus_fp64_over_fp64_error": g.get("ratio"), "max_ratio": g.get("max_ratio"),
+            "reference": g.get("reference"), "criterion": "max_ratio <= 0.05",
+            "other_grids": {k: v.get("max_ratio") for k, v in rec["grids"].items() if k != str(n)},
+            "record": "results/tgv_equal_l2.json",
+            "stale": rec.get("kernel_sources_sha256") != equal_l2.kernel_digest()}
 
 
 def main():
@@ -143,7 +182,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -239,6 +278,9 @@ def main():
             a64 = per_cell * N / (m64 / max(c64, 1) * 1e-3) / 1e12
             line["fp64_plain"]["flux_roofline"] = {"achieved": round(a64, 3), "peak": PEAK_TFLOPS["fp64"],
                                                    "frac": round(a64 / PEAK_TFLOPS["fp64"], 4)}
+    eq = equal_l2_record(n)
+    if eq is not None:
+        line["equal_l2"] = eq
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

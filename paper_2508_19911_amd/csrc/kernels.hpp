@@ -633,20 +633,29 @@ __global__ __launch_bounds__(BLK) void k_update2(Grid g, const double* __restric
 }
 
 // ============================================================================ reductions
-// block reduction in shared memory (fixed tree: deterministic)
+// Reduction of NV values over a block: first over the 64 lanes of each wave by cross-lane exchanges in
+// a fixed butterfly (lane i combines with lane i ^ 32, ^ 16, ..., ^ 1; the operations are commutative,
+// so every lane ends with the same bits), then over the block's waves through LDS, in wave order.  The
+// order is the same on every run: the reductions are deterministic.
+constexpr int WAVES = BLK / 64;
 template <int NV, class Op>
-__device__ __forceinline__ void block_reduce(double (*sh)[BLK], double* val, Op op) {
+__device__ __forceinline__ void block_reduce(double (*sh)[WAVES], double* val, Op op) {
 #pragma unroll
-  for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = val[q];
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) val[q] = op(q, val[q], __shfl_xor(val[q], off, 64));
+  const int w = (int)(threadIdx.x >> 6);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) sh[q][w] = val[q];
   __syncthreads();
-  for (int s = BLK / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s)
 #pragma unroll
-      for (int q = 0; q < NV; ++q) sh[q][threadIdx.x] = op(q, sh[q][threadIdx.x], sh[q][threadIdx.x + s]);
-    __syncthreads();
+  for (int q = 0; q < NV; ++q) {
+    double r = sh[q][0];
+#pragma unroll
+    for (int k = 1; k < WAVES; ++k) r = op(q, r, sh[q][k]);
+    val[q] = r;
   }
-#pragma unroll
-  for (int q = 0; q < NV; ++q) val[q] = sh[q][0];
 }
 
 struct DtOp {
@@ -655,14 +664,14 @@ struct DtOp {
   }
 };
 
-// per block: min_i min_d h_d/(|U_d|+c), max nu, any non-physical cell
+// per block: min_i min_d h_d/(|U_d|+c), max nu, any non-physical cell, over the cells
+// blockIdx.x * BLK + threadIdx.x + m gridDim.x BLK (one cell per thread when the grid covers N)
 __global__ __launch_bounds__(BLK) void k_dt(Grid g, const double* __restrict__ Q, FluxParams fp,
                                             double* part) {
-  __shared__ double sh[3][BLK];
-  const int cell = blockIdx.x * BLK + threadIdx.x;
+  __shared__ double sh[3][WAVES];
   double val[3] = {INFINITY, 0.0, 0.0};
-  if (cell < g.N) {
-    const long long N = g.N;
+  const long long N = g.N;
+  for (long long cell = (long long)blockIdx.x * BLK + threadIdx.x; cell < N; cell += (long long)gridDim.x * BLK) {
     const double rho = Q[cell], mx = Q[N + cell], my = Q[2 * N + cell], mz = Q[3 * N + cell],
                  E = Q[4 * N + cell];
     const double U = mx / rho, V = my / rho, W = mz / rho;
@@ -670,8 +679,8 @@ __global__ __launch_bounds__(BLK) void k_dt(Grid g, const double* __restrict__ Q
     const bool ok = rho > 0.0 && p > 0.0 && isfinite(p) && isfinite(U) && isfinite(V) && isfinite(W);
     if (ok) {
       const double c = sqrt(fp.gamma * p / rho);
-      val[0] = fmin(g.h[0] / (fabs(U) + c), fmin(g.h[1] / (fabs(V) + c), g.h[2] / (fabs(W) + c)));
-      if (fp.mu0 > 0.0) val[1] = viscosity<double>(fp, p / rho) / rho;
+      val[0] = fmin(val[0], fmin(g.h[0] / (fabs(U) + c), fmin(g.h[1] / (fabs(V) + c), g.h[2] / (fabs(W) + c))));
+      if (fp.mu0 > 0.0) val[1] = fmax(val[1], viscosity<double>(fp, p / rho) / rho);
     } else {
       val[2] = 1.0;
     }
@@ -686,7 +695,7 @@ __global__ __launch_bounds__(BLK) void k_dt(Grid g, const double* __restrict__ Q
 
 __global__ __launch_bounds__(BLK) void k_dt_final(int nblk, const double* __restrict__ part,
                                                   double* out) {
-  __shared__ double sh[3][BLK];
+  __shared__ double sh[3][WAVES];
   double val[3] = {INFINITY, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblk; b += BLK) {
     val[0] = fmin(val[0], part[b * 3 + 0]);
@@ -761,7 +770,7 @@ __global__ __launch_bounds__(BLK) void k_diag(Grid g, const double* __restrict__
                                               const T* __restrict__ G,
                                               const unsigned char* __restrict__ flags,
                                               FluxParams fp, double vol, double* part) {
-  __shared__ double sh[11][BLK];
+  __shared__ double sh[11][WAVES];
   const int cell = blockIdx.x * BLK + threadIdx.x;
   double val[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, INFINITY, INFINITY};
   if (cell < g.N) {
@@ -815,7 +824,7 @@ __global__ __launch_bounds__(BLK) void k_diag(Grid g, const double* __restrict__
 
 __global__ __launch_bounds__(BLK) void k_diag_final(int nblk, const double* __restrict__ part,
                                                     double* out) {
-  __shared__ double sh[11][BLK];
+  __shared__ double sh[11][WAVES];
   double val[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, INFINITY, INFINITY};
   for (int b = threadIdx.x; b < nblk; b += BLK)
 #pragma unroll
@@ -853,7 +862,7 @@ __device__ __forceinline__ void quad_point(const FluxParams& fp, double w, const
 }
 
 __device__ __forceinline__ void quad_partials(double* part, double* acc) {
-  __shared__ double sh[11][BLK];
+  __shared__ double sh[11][WAVES];
   double val[11] = {acc[0], acc[1], acc[2], 0, 0, 0, 0, 0, 0, INFINITY, INFINITY};
   block_reduce<11>(sh, val, DiagOp{});
   if (threadIdx.x == 0)
