@@ -195,6 +195,23 @@ int cgks_indicator_train(void* ctx, const void* dev_x, const void* dev_y, long n
 int cgks_indicator_grad(void* ctx, const void* dev_x, const void* dev_y, long n, double* loss,
                         double* grad);
 
+/* ---- no device allocation ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the time step of cgks_compute_dt for a state the caller holds on
+ * the device, with no context and no workspace.  q_dev: Q[5][N] (FP64, the layout of cgks_set_state)
+ * for the grid and parameters p; dt_dev: caller-owned device output of 2 doubles, dt_dev[0] = the
+ * time step at CFL number cfl (CFL and viscous limits), dt_dev[1] = 1.0 if a cell is non-physical
+ * (rho <= 0, p <= 0 or NaN; dt_dev[0] is then not meaningful), else 0.0.  The kernels run on
+ * hip_stream (NULL: the null stream) and the call returns without waiting for them.  The reduction's
+ * block partials live in a static device array of the library (about 48 KiB per device, kept until
+ * the process ends), which bounds the reduction to 2048 blocks; any N that cgks_workspace_bytes
+ * accepts is handled (threads then fold several cells).  The call allocates nothing.  Every call on a
+ * device shares that array: calls that overlap in time on one device race.  EINVAL for bad parameters
+ * (as cgks_workspace_bytes), NULL pointers or cfl <= 0; EDEVICE if the array's device address cannot
+ * be found or a launch fails. */
+int cgks_compute_dt_noalloc(const cgks_params* p, const double* q_dev, void* hip_stream, double cfl,
+                            double* dt_dev);
+
 /* ---- kernel timing ---------------------------------------------------------------------------------
  * When enabled, the sweep's kernel launches of the selected classes are bracketed by HIP events on the
  * context's stream.  cgks_timing_read synchronises the stream and returns, per kernel class, the number

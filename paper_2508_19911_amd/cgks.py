@@ -25,7 +25,7 @@ ERRORS = {0: "ok", -1: "EINVAL", -2: "EWORKSPACE", -3: "EDEVICE", -4: "ENONPHYSI
 SYMBOLS = [
     "cgks_workspace_bytes", "cgks_create", "cgks_destroy", "cgks_set_state", "cgks_set_ic", "cgks_ic_host",
     "cgks_get_state", "cgks_compute_dt", "cgks_step", "cgks_step_fixed", "cgks_stage", "cgks_stage_sampled",
-    "cgks_stage_advance", "cgks_halo_exchange_z",
+    "cgks_stage_advance", "cgks_halo_exchange_z", "cgks_compute_dt_noalloc",
     "cgks_diagnostics", "cgks_diagnostics_quad", "cgks_get_flags", "cgks_indicator_set", "cgks_indicator_get",
     "cgks_features", "cgks_indicator_logits", "cgks_labels", "cgks_indicator_train",
     "cgks_indicator_grad", "cgks_timing_enable", "cgks_timing_read", "cgks_debug_point_flux",
@@ -83,6 +83,7 @@ def load():
     L.cgks_set_ic.argtypes = [P, I, P, I, ctypes.c_uint64]
     L.cgks_ic_host.argtypes = [pp, I, P, I, ctypes.c_uint64, P, P]
     L.cgks_stage_advance.argtypes = [P, I, D]
+    L.cgks_compute_dt_noalloc.argtypes = [pp, P, P, D, P]
     L.cgks_halo_exchange_z.argtypes = [P, P, I, I]
     L.cgks_get_state.argtypes = [P, P, P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long)]
     L.cgks_compute_dt.argtypes = [P, D, ctypes.POINTER(D)]

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -40,6 +41,19 @@ bool valid(const cgks_params* p) {
   if (p->precision != CGKS_PREC_FP64 && p->precision != CGKS_PREC_FP32_BULK) return false;
   if (p->mu0 < 0.0) return false;
   return true;
+}
+
+Grid make_grid(const cgks_params* p) {
+  Grid g;
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.nz = p->nz;
+  g.N = (long long)p->nx * p->ny * p->nz;
+  g.h[0] = p->lx / p->nx;
+  g.h[1] = p->ly / p->ny;
+  g.h[2] = p->lz / p->nz;
+  for (int d = 0; d < 3; ++d) g.ih[d] = 1.0 / g.h[d];
+  return g;
 }
 
 Layout layout(const cgks_params* p) {
@@ -369,14 +383,7 @@ int cgks_create(const cgks_params* p, void* ws, size_t bytes, void* stream, void
   c->L = L;
   c->ws = static_cast<char*>(ws);
   c->stream = static_cast<hipStream_t>(stream);
-  c->g.nx = p->nx;
-  c->g.ny = p->ny;
-  c->g.nz = p->nz;
-  c->g.N = (long long)p->nx * p->ny * p->nz;
-  c->g.h[0] = p->lx / p->nx;
-  c->g.h[1] = p->ly / p->ny;
-  c->g.h[2] = p->lz / p->nz;
-  for (int d = 0; d < 3; ++d) c->g.ih[d] = 1.0 / c->g.h[d];
+  c->g = make_grid(p);
   c->fp = make_flux_params(p->gamma, p->mu0, p->sutherland_tref, p->prandtl, p->tau_eps, p->tau_c);
   c->gp.dH = p->geno_dh;
   c->gp.eps = p->geno_eps;
@@ -1048,6 +1055,58 @@ int cgks_debug_coefficients(void* ctx, double* out) {
   if (!rc) rc = launch_coef<float>(c, c.at<double>(c.L.Q), c.at<float>(c.L.G));
   if (rc) return rc;
   return copy_coefficients<float>(c, out);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- no-allocation time step
+// The device scratch of cgks_compute_dt_noalloc: the block partials of the time-step reduction (3 per
+// block, at most DT_NOALLOC_BLOCKS blocks) and the reduced limits (3 more).  One copy per device, held
+// until the process ends and shared by every call on that device.  Host code never uses the array's
+// name as an address: the device address comes from hipGetSymbolAddress, once per device.
+constexpr int DT_NOALLOC_BLOCKS = 2048;
+static __device__ __align__(256) double scratch[3 * DT_NOALLOC_BLOCKS + 3];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;  // the address of `scratch` on device d (nullptr: not looked up yet)
+
+// the device address of `scratch` on the current device
+int scratch_address(double** out) {
+  int dev = 0;
+  HIPCK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+  if (!g_scratch_dev[dev]) {
+    void* a = nullptr;
+    HIPCK(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+    if (!a) return dev_error("hipGetSymbolAddress", hipErrorInvalidSymbol);
+    g_scratch_dev[dev] = static_cast<double*>(a);
+  }
+  *out = g_scratch_dev[dev];
+  return CGKS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int cgks_compute_dt_noalloc(const cgks_params* p, const double* q_dev, void* hip_stream, double cfl,
+                            double* dt_dev) {
+  if (!valid(p) || !q_dev || !dt_dev || !(cfl > 0.0)) return CGKS_EINVAL;
+  double* part = nullptr;
+  const int rc = scratch_address(&part);
+  if (rc) return rc;
+  double* lim = part + 3 * DT_NOALLOC_BLOCKS;
+  const Grid g = make_grid(p);
+  const FluxParams fp = make_flux_params(p->gamma, p->mu0, p->sutherland_tref, p->prandtl, p->tau_eps, p->tau_c);
+  const int nb = (int)std::min<long long>((g.N + BLK - 1) / BLK, DT_NOALLOC_BLOCKS);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const double hmin = std::fmin(g.h[0], std::fmin(g.h[1], g.h[2]));
+  k_dt<<<nb, BLK, 0, st>>>(g, q_dev, fp, part);
+  k_dt_final<<<1, BLK, 0, st>>>(nb, part, lim);
+  k_dt_value<<<1, 64, 0, st>>>(lim, cfl, hmin, p->mu0 > 0.0 ? 1 : 0, dt_dev);
+  LAUNCHCK("cgks_compute_dt_noalloc");
+  return CGKS_OK;
 }
 
 const char* cgks_strerror(int code) {

@@ -757,6 +757,15 @@ __global__ void k_step_control(const double* __restrict__ lim, double* ctl, doub
   if (t_stop > 0.0 && t + dt > t_stop) dt = t_stop - t;
   ctl[0] = dt;
 }
+// dt[0] = the time step of the limits lim (as k_step_control, without a t_stop), dt[1] = the
+// non-physical flag of the reduction
+__global__ void k_dt_value(const double* __restrict__ lim, double cfl, double hmin, int viscous, double* dt) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double d = cfl * lim[0];
+  if (viscous) d = fmin(d, cfl * hmin * hmin / (3.0 * lim[1]));
+  dt[0] = d;
+  dt[1] = lim[2];
+}
 __global__ void k_step_advance(double* ctl) {
   if (threadIdx.x == 0 && blockIdx.x == 0 && ctl[1] == 0.0) {
     ctl[2] += ctl[0];
