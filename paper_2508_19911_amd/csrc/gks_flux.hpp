@@ -213,6 +213,16 @@ __host__ __device__ __forceinline__ T viscosity(const FluxParams& P, T Temp) {
   return T(P.mu0);
 }
 
+// Values of the FP64 phase that the flux needs again only at its end (G0, SP0 - G0 and the two sides'
+// equilibrium interface parts) can be parked outside the registers while the slope products run:
+// NoPark keeps them in registers; a kernel may pass a parking place of its own (LDS).
+struct NoPark {
+  template <class D, class T>
+  __host__ __device__ void save(const D*, const T*, const T*, const T*) {}
+  template <class D, class T>
+  __host__ __device__ void load(D*, T*, T*, T*) {}
+};
+
 // conversion between the FP64 type D and the bulk type T (the identity when they are one type)
 template <class T, class D>
 __host__ __device__ __forceinline__ T bulk(D x) {
@@ -234,10 +244,11 @@ __host__ __device__ __forceinline__ T bulk(D x) {
 // the moment products are sparse; the results are shifted back to the lab before they are summed.
 // Slopes are solved from the density-weighted derivatives directly (b = rho a), so every piece comes
 // out density-weighted without a division.
-template <class T, bool IFACE, class D = double>
+template <class T, bool IFACE, class D = double, class Park = NoPark>
 __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt, const double* Q0L,
                                                   const T* VL, const T* DL, const double* Q0R,
-                                                  const T* VR, const T* DR, D* Fn, T* out) {
+                                                  const T* VR, const T* DR, D* Fn, T* out,
+                                                  Park park = Park()) {
   const T K = T(P.Kdof);
   const T ik3 = T(P.ik3);
   const D gm1 = D(P.gamma - 1.0);
@@ -319,6 +330,10 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
       oR[v] = w1 * bulk<T>(W0[v] - data<D>(Q0R[v])) + w * VR[v];
     }
   }
+  D G0p[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) G0p[v] = G0[v];
+  park.save(G0p, dS, oL, oR);
 
   // lab sums over the two sides, each piece density-weighted on its half space:
   // dW0[d] = <a_d psi>, SP = {-, <u (a.u) psi>, <u A psi>, -, <(a.u) psi>, <A psi>}
@@ -472,6 +487,7 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
   ct[4] = -ct[1];
   ct[5] = T(4) * rom * rom;
 
+  park.load(G0p, dS, oL, oR);
   // F^n = (1 - cn3) G0 + cn3 SP0 + the slope and time-derivative products = G0 (FP64) + dF (T);
   // F_t = ct0 (G0 - SP0) + ...
   T dF[5];
@@ -495,7 +511,7 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
     dF[4] = dF[4] + T(1.0 / P.prandtl - 1.0) * (qf - p0.U * qq);
   }
 #pragma unroll
-  for (int v = 0; v < 5; ++v) Fn[v] = G0[v] + bulk<D>(dF[v]);
+  for (int v = 0; v < 5; ++v) Fn[v] = G0p[v] + bulk<D>(dF[v]);
   if constexpr (IFACE) {
     const T ctq = ct[1] - ct[2];
 #pragma unroll

@@ -274,6 +274,43 @@ struct FluxShared {
   T D[FLUX_FACES][4][10][3];     // face-frame derivatives, physical units
 };
 
+// Parking place of the flux's FP64-phase values in the derivative area of FluxShared, once every lane
+// has read its point's derivatives: [value][lane], so a wave's accesses are contiguous (no bank
+// conflicts).  The barriers keep the stores and loads where they are written.
+template <class T>
+struct LdsPark {
+  char* area;
+  int lane;
+  __device__ void save(const double* G0, const T* dS, const T* oL, const T* oR) const {
+    double* d = reinterpret_cast<double*>(area);
+    T* t = reinterpret_cast<T*>(area + 5 * FLUX_BLK * sizeof(double));
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      d[v * FLUX_BLK + lane] = G0[v];
+      t[v * FLUX_BLK + lane] = dS[v];
+      t[(5 + v) * FLUX_BLK + lane] = oL[v];
+      t[(10 + v) * FLUX_BLK + lane] = oR[v];
+    }
+  }
+  __device__ void load(double* G0, T* dS, T* oL, T* oR) const {
+    const double* d = reinterpret_cast<const double*>(area);
+    const T* t = reinterpret_cast<const T*>(area + 5 * FLUX_BLK * sizeof(double));
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      G0[v] = d[v * FLUX_BLK + lane];
+      dS[v] = t[v * FLUX_BLK + lane];
+      oL[v] = t[(5 + v) * FLUX_BLK + lane];
+      oR[v] = t[(10 + v) * FLUX_BLK + lane];
+    }
+  }
+};
+static_assert(5 * FLUX_BLK * sizeof(double) + 15 * FLUX_BLK * sizeof(float) <= sizeof(FluxShared<float>::D),
+              "parking area");
+static_assert(5 * FLUX_BLK * sizeof(double) + 15 * FLUX_BLK * sizeof(double) <= sizeof(FluxShared<double>::D),
+              "parking area");
+
 // Occupancy (measured at 128^3): the FP32 form asks for three waves per SIMD, which spills about a
 // dozen registers held across the slope products (0.651 ms per launch against 0.688 at two waves
 // without spills); FP64 runs at one wave with every value in registers (1.40 ms per launch against
@@ -348,7 +385,8 @@ __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 1 : 3) void k_flux5(Grid
   }
   double Fn[5];
   T out[25];
-  gks_flux<T, true>(fp, dt, QL0, VL, DL, QR0, VR, DR, Fn, out);
+  gks_flux<T, true>(fp, dt, QL0, VL, DL, QR0, VR, DR, Fn, out,
+                    LdsPark<T>{reinterpret_cast<char*>(&sh.D[0][0][0][0]), (int)threadIdx.x});
   // 2x2 Gauss average over the four lanes of the face
 #pragma unroll
   for (int n = 0; n < 5; ++n) Fn[n] = 0.25 * quad_sum(Fn[n]);
