@@ -69,6 +69,19 @@ __host__ __device__ __forceinline__ double rsqrt64(double x) {
 #endif
 }
 
+// 1/x in FP64: the hardware FP32 estimate refined by two Newton steps (error of an ulp or two for x in
+// the normal FP32 range; the IEEE division costs about twice the instructions); the host build divides.
+__host__ __device__ __forceinline__ double rcp64(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double y = (double)__builtin_amdgcn_rcpf((float)x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+#else
+  return 1.0 / x;
+#endif
+}
+
 // The split at u = 0 of a Maxwellian's normal velocity (mean U, variance var = p/rho), in FP64:
 // pp = P(u > 0) = erfc(-x)/2 and pm = P(u < 0) = erfc(x)/2 with x = U/sqrt(2 var), and
 // tail = e^{-x^2} sqrt(var/(2 pi)), so that <u>_{u>0} = U pp + tail and <u>_{u<0} = U pm - tail.
@@ -222,20 +235,43 @@ struct BufPlane {
   }
 };
 
+// A store of element idx of a plane of n elements through a buffer resource made for the plane: the
+// plane's base sits in scalar registers and the lane supplies a 32-bit byte offset, so a run of stores
+// into many planes at one offset needs no per-lane 64-bit address arithmetic.
+template <class T>
+__device__ __forceinline__ void st_plane(T* base, long long n, uint32_t idx, T v) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      base, (short)0, (int)(uint32_t)(n * (long long)sizeof(T)), BUFFER_RSRC_WORD3);
+  if constexpr (sizeof(T) == 8) {
+    using B64 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B64, v), r, (int)(idx * 8u), 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)(idx * 4u), 0, 0);
+  }
+#else
+  base[idx] = v;
+#endif
+}
+
 // Exchange inside a quad of lanes (DPP quad_perm, a VALU operand modifier; no LDS traffic):
-// QUAD_XOR1 = lanes (1,0,3,2), QUAD_XOR2 = lanes (2,3,0,1).
+// QUAD_XOR1 = lanes (1,0,3,2), QUAD_XOR2 = lanes (2,3,0,1).  Every lane of a quad has a source lane,
+// so the moved value never falls back to the "old" operand; passing the source itself there (with
+// bound_ctrl) lets the compiler fold the move into the consuming add.
 constexpr int QUAD_XOR1 = 1 | (0 << 2) | (3 << 4) | (2 << 6);
 constexpr int QUAD_XOR2 = 2 | (3 << 2) | (0 << 4) | (1 << 6);
 template <int CTRL>
 __device__ __forceinline__ float quad_perm(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+  const int b = __builtin_bit_cast(int, x);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double quad_perm(double x) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+  const int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+  const int plo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, true);
+  const int phi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)phi << 32) | (unsigned)plo);
 }
 // sum over the 4 lanes of a quad, in the order (x + x^1) + (x + x^1)^2
 template <class T>

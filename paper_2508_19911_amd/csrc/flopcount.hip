@@ -105,6 +105,13 @@ inline Fl dexp(Fl x) { return un('e', x, std::exp(x.v())); }
 inline Fl dexpm1(Fl x) { return un('x', x, std::expm1(x.v())); }
 inline Fl derfc(Fl x) { return un('r', x, std::erfc(x.v())); }
 inline Fl drcp(Fl x) { return mkf('/', Fl(1.0), x, 1.0 / x.v()); }
+// FP64 reciprocal of the device: a hardware estimate (1 transcendental) and two Newton steps
+inline Fl rcp64(Fl x) {
+  Fl y = un('c', x, 1.0 / x.v());
+  y = fma(y, fma(-x, y, Fl(1.0)), y);
+  y = fma(y, fma(-x, y, Fl(1.0)), y);
+  return y;
+}
 // FP64 reciprocal square root of the device: a hardware estimate (1 transcendental) and two Newton
 // steps, written out so that their operations are counted
 inline Fl rsqrt64(Fl x) {

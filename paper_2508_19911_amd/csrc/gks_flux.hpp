@@ -267,7 +267,7 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const D rho = Ws[s][0];
-    const D ir = D(1) / rho;
+    const D ir = rcp64(rho);
     const D U = Ws[s][1] * ir, V = Ws[s][2] * ir, W = Ws[s][3] * ir;
     const D p = gm1 * (Ws[s][4] - D(0.5) * rho * (U * U + V * V + W * W));
     const D var = p * ir;
@@ -303,7 +303,7 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
 
   // interface equilibrium g0: primitives and Euler flux G0 = rho0 <u psi> in FP64; the difference
   // SP0 - G0 of the two equilibrium fluxes is small where the flow is smooth and goes on in T
-  const D ir0 = D(1) / W0[0];
+  const D ir0 = rcp64(W0[0]);
   const D U0 = W0[1] * ir0, V0 = W0[2] * ir0, Wv0 = W0[3] * ir0;
   const D p064 = gm1 * (W0[4] - D(0.5) * W0[0] * (U0 * U0 + V0 * V0 + Wv0 * Wv0));
   const D G0[5] = {W0[1], W0[1] * U0 + p064, W0[1] * V0, W0[1] * Wv0, U0 * (W0[4] + p064)};

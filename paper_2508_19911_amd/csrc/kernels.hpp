@@ -328,10 +328,13 @@ __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 1 : 3) void k_flux5(Grid
   using V = typename Vec16<T>::type;
   const int kgp = threadIdx.x & 3;
   const int fl = threadIdx.x >> 2;
-  // x faces: the low neighbour of a block's first cell lies in the previous block, so contiguous
-  // block ranges per XCD keep it in the same L2.  y and z faces keep the hardware's round-robin
-  // order: their neighbour blocks (nx/16 and nx ny/16 blocks back) are then on the same XCD and only
-  // 1/8 as far back in its order, inside the L2.
+  // Block order, so that the low neighbour's coefficients are still in the L2 of the block's XCD:
+  // every XCD takes a contiguous range of logical blocks (xcd_remap), and logical blocks run along
+  // the face normal.  x faces: a block's 16 cells are a run along x, so the low neighbour of its
+  // first cell lies in the previous block.  y and z faces (rows whose length is a multiple of 16):
+  // logical block b is the 16-cell run (b / n_d, in x-fastest run order without axis d) at
+  // position b mod n_d along d, so consecutive blocks step along d and each reads the coefficients
+  // its predecessor read as its own.  Other row lengths keep the linear order.
   const unsigned blk = DIR == 0 ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   int cell = (int)blk * FLUX_FACES + fl;
   const bool active = cell < g.N;
@@ -393,21 +396,17 @@ __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 1 : 3) void k_flux5(Grid
 #pragma unroll
   for (int n = 0; n < 25; ++n) out[n] = T(0.25) * quad_sum(out[n]);
   if (active) {
-    // output n = 5 * block + face-frame variable: block 0 is F^n (FP64 planes), blocks 1..5 are
-    // F_t, Q^l_n - Q0^l, Q^l_t, Q^r_n - Q0^r, Q^r_t (T planes); each lane stores a quarter
+    // every lane of a face holds the face's sums; all four store them (the four lanes of a face
+    // write the same bytes, which the store merges), so no lane branches on its output.  F^n goes to
+    // the FP64 planes, then F_t, Q^l_n - Q0^l, Q^l_t, Q^r_n - Q0^r, Q^r_t to the T planes.
 #pragma unroll
-    for (int blk = 0; blk < 6; ++blk)
+    for (int vf = 0; vf < 5; ++vf) {
+      const int vg = (vf >= 1 && vf <= 3) ? 1 + perm(DIR, vf - 1) : vf;
+      st_plane(Fd + (DIR * 5 + vg) * N, N, (uint32_t)cell, Fn[vf]);
 #pragma unroll
-      for (int vf = 0; vf < 5; ++vf) {
-        const int vg = (vf >= 1 && vf <= 3) ? 1 + perm(DIR, vf - 1) : vf;
-        const int n = blk * 5 + vf;
-        if ((n & 3) == kgp) {
-          if (blk == 0)
-            st(Fd + (DIR * 5 + vg) * N, (uint32_t)cell, Fn[vf]);
-          else
-            st(Fb + (DIR * 25 + (blk - 1) * 5 + vg) * N, (uint32_t)cell, out[n - 5]);
-        }
-      }
+      for (int blk = 0; blk < 5; ++blk)
+        st_plane(Fb + (DIR * 25 + blk * 5 + vg) * N, N, (uint32_t)cell, out[blk * 5 + vf]);
+    }
   }
 }
 

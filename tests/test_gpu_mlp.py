@@ -62,6 +62,25 @@ def test_logits_match_oracle_bf16():
     assert np.median(np.abs(zg - zo)) <= 1e-4 * scale
 
 
+@pytest.mark.parametrize("dims", [(70, 5, 3), (64, 2, 2), (9, 7, 6)])
+def test_fp32_inference_ragged_matches_oracle(dims):
+    """FP32-bulk inference (FP64 averages, FP32 gradients): its logits against the oracle's BF16
+    emulation on the per-cell features of the same state, on grids whose rows are not multiples of the
+    256-cell block and on a grid smaller than one block, at the bar of the FP64 form's test."""
+    nx, ny, nz = dims
+    case = inputs.tgv_case(8, ma=0.3).with_(nx=nx, ny=ny, nz=nz, lx=0.05 * nx, ly=0.3 * ny, lz=0.4 * nz)
+    st = inputs.seeded_smooth_state(case, seed=7, amp=0.3)
+    s = cg().Solver(case, precision=1); s.set_state(*st)
+    p = rand_params(3)
+    s.indicator_set(p, 0.0)
+    zg = s.logits()
+    zo = oracle.mlp_forward(p, s.features(), bf16=True)
+    scale = max(np.abs(zo).max(), 1.0)
+    assert np.abs(zg - zo).max() <= 1e-2 * scale, np.abs(zg - zo).max()
+    assert np.median(np.abs(zg - zo)) <= 1e-4 * scale
+    s.close()
+
+
 def test_gradient_matches_oracle():
     import torch
     cgks = cg()

@@ -77,6 +77,8 @@ CASES = {
     "tgv8": lambda: (inputs.tgv_case(8), None),
     "ragged_viscous": lambda: (inputs.tgv_case(8, ma=0.3).with_(nx=13, ny=7, nz=5, lx=3.1, ly=1.9, lz=1.3), 11),
     "ragged_inviscid": lambda: (inputs.vortex_case(8).with_(nx=11, ny=9, nz=3, lz=2.0), 12),
+    # rows a multiple of the flux block (16 cells) long, ny != nz: no ragged flux block
+    "rows16_viscous": lambda: (inputs.tgv_case(8, ma=0.3).with_(nx=32, ny=6, nz=10, lx=3.3, ly=1.1, lz=1.7), 14),
 }
 
 
