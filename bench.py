@@ -39,22 +39,19 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector peaks (FP32 packed-math figure)
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per k_flux5<float> launch on the 128^3 grid (mean over the three directions, read +
+# HBM bytes per k_flux5<float> launch on the 256^3 grid (mean over the three directions, read +
 # write), from two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE) scaled by a 1 GiB copy
-# kernel: profiles/flux_tgv128_hbm_counters.md.  Valid only for the kernel sources they were taken
-# on; any change to those sources makes the reported traffic null until the counters are retaken.
-FLUX_TRAFFIC = {"grid": 128, "bytes_per_launch": 1.8717e+09,
-                "sources_sha256": "a727b21021755f2b83ceaca43414733d47354cee5f525a851e3facf22f91c667"}
+# kernel: profiles/step_tgv256_hbm_counters.md.  Valid only for the kernel code they were taken on
+# (comments aside); any change to that code makes the reported traffic null until the counters are
+# retaken.
+FLUX_TRAFFIC = {"grid": 256, "bytes_per_launch": 1.9480e+10,
+                "sources_sha256": "a6f0a1aaec54071851c6732a4d65c9f738e7f01a4318a3659f83973bf22a6ba6"}
 KERNEL_SOURCES = ["common.hpp", "gks_flux.hpp", "recon.hpp", "recon_tables.hpp", "kernels.hpp"]
 
 
 def kernel_digest():
-    import hashlib
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2508_19911_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+    from paper_2508_19911_amd import equal_l2
+    return equal_l2.source_digest(KERNEL_SOURCES)
 
 
 def load_flops():

@@ -263,7 +263,7 @@ __global__ __launch_bounds__(BLK) void k_coef(Grid g, const double* __restrict__
 //     evaluates its polynomial at all 4 Gauss points at once (parity classes) and writes the
 //     point states to LDS.
 //  2. Each lane reads the two states of its own point and evaluates the gas-kinetic flux.
-//  3. The 2x2 Gauss average is a 4-lane reduction; each lane stores a quarter of the 30 outputs.
+//  3. The 2x2 Gauss average is a 4-lane reduction; all four lanes store the face's 30 outputs.
 constexpr int FLUX_FACES = 16;
 constexpr int FLUX_BLK = 4 * FLUX_FACES;
 
@@ -311,10 +311,11 @@ static_assert(5 * FLUX_BLK * sizeof(double) + 15 * FLUX_BLK * sizeof(float) <= s
 static_assert(5 * FLUX_BLK * sizeof(double) + 15 * FLUX_BLK * sizeof(double) <= sizeof(FluxShared<double>::D),
               "parking area");
 
-// Occupancy (measured at 128^3): the FP32 form asks for three waves per SIMD, which spills about a
-// dozen registers held across the slope products (0.651 ms per launch against 0.688 at two waves
-// without spills); FP64 runs at one wave with every value in registers (1.40 ms per launch against
-// 1.47 at two waves, where 55 registers spill).
+// Occupancy: the FP32 form asks for three waves per SIMD (at most 168 VGPRs; with the FP64-phase
+// values parked in LDS it needs 135 and no scratch); FP64 asks for one and keeps every value in
+// registers (at two waves, 55 registers spilled and the launch took 5% longer).  A block is one wave:
+// with two waves per block (32 faces, the polynomials dealt out so that one wave skips the half-idle
+// third round) the barriers between the phases made the launch 12% slower.
 template <class T, int DIR>
 __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 1 : 3) void k_flux5(Grid g, const double* __restrict__ Q,
                                                     const T* __restrict__ C, double* __restrict__ Fd,
@@ -328,13 +329,12 @@ __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 1 : 3) void k_flux5(Grid
   using V = typename Vec16<T>::type;
   const int kgp = threadIdx.x & 3;
   const int fl = threadIdx.x >> 2;
-  // Block order, so that the low neighbour's coefficients are still in the L2 of the block's XCD:
-  // every XCD takes a contiguous range of logical blocks (xcd_remap), and logical blocks run along
-  // the face normal.  x faces: a block's 16 cells are a run along x, so the low neighbour of its
-  // first cell lies in the previous block.  y and z faces (rows whose length is a multiple of 16):
-  // logical block b is the 16-cell run (b / n_d, in x-fastest run order without axis d) at
-  // position b mod n_d along d, so consecutive blocks step along d and each reads the coefficients
-  // its predecessor read as its own.  Other row lengths keep the linear order.
+  // x faces: the low neighbour of a block's first cell lies in the previous block, so contiguous
+  // block ranges per XCD keep it in the same L2.  y and z faces keep the hardware's round-robin
+  // order: their neighbour blocks (nx/16 and nx ny/16 blocks back) are then on the same XCD when those
+  // counts are multiples of 8, and only 1/8 as far back in its order.  (Running the y and z blocks
+  // along the normal inside each XCD's range halves the z launch's reads, but the launch is ALU-bound
+  // and took longer.)
   const unsigned blk = DIR == 0 ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   int cell = (int)blk * FLUX_FACES + fl;
   const bool active = cell < g.N;

@@ -22,6 +22,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import time
 
 import numpy as np
@@ -32,12 +33,21 @@ KERNEL_SOURCES = ["common.hpp", "gks_flux.hpp", "recon.hpp", "recon_tables.hpp",
 FIELDS = ["rho", "U", "V", "W", "p"]
 
 
-def kernel_digest():
+def source_digest(names):
+    """SHA-256 of the code of the given csrc files with comments and layout taken out, so that a
+    record stays valid across edits that change no code."""
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(HERE, "csrc", name), "rb") as f:
-            h.update(f.read())
+    for name in names:
+        with open(os.path.join(HERE, "csrc", name), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
+
+
+def kernel_digest():
+    return source_digest(KERNEL_SOURCES)
 
 
 def prims(q, gamma):
