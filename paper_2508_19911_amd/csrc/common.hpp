@@ -59,10 +59,11 @@ __host__ __device__ __forceinline__ float dexpm1(float x) {
 // few 1e-16 for x in the normal FP32 range); the host build uses the C library.
 __host__ __device__ __forceinline__ double rsqrt64(double x) {
 #ifdef __HIP_DEVICE_COMPILE__
+  // Newton step y <- y + y (1/2 - x y^2 / 2): its constants are inline operands of the FP64 FMA
   double y = (double)__builtin_amdgcn_rsqf((float)x);
-  const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
+  const double mhx = -0.5 * x;
+  y = fma(y, fma(mhx * y, y, 0.5), y);
+  y = fma(y, fma(mhx * y, y, 0.5), y);
   return y;
 #else
   return 1.0 / sqrt(x);
@@ -82,48 +83,46 @@ __host__ __device__ __forceinline__ double rcp64(double x) {
 #endif
 }
 
+// Coefficients of normal_split's two Maclaurin series, highest order first (Horner): erf(x) =
+// (2/sqrt(pi)) x sum_n y^n / (n! (2n+1)), n = 0..11, and e^y = sum_n y^n / n!, n = 0..12, with y = -x^2.
+// Kernels receive them as an argument, so they sit in scalar registers: an FP64 FMA takes no literal
+// operand on this architecture, and as literals every one cost two vector moves per use.
+struct SplitSeries {
+  double erf_c[12];
+  double exp_c[13];
+};
+inline SplitSeries make_split_series() {
+  SplitSeries s;
+  double fact = 1.0;  // n!, exact in FP64 for these n
+  for (int n = 0; n <= 12; ++n) {
+    if (n > 0) fact *= n;
+    if (n <= 11) s.erf_c[11 - n] = 1.0 / (fact * (2 * n + 1));
+    s.exp_c[12 - n] = 1.0 / fact;
+  }
+  return s;
+}
+
 // The split at u = 0 of a Maxwellian's normal velocity (mean U, variance var = p/rho), in FP64:
 // pp = P(u > 0) = erfc(-x)/2 and pm = P(u < 0) = erfc(x)/2 with x = U/sqrt(2 var), and
 // tail = e^{-x^2} sqrt(var/(2 pi)), so that <u>_{u>0} = U pp + tail and <u>_{u<0} = U pm - tail.
 // For |x| < 1/2 (every point of a low-Mach flow) erf(x) and e^{-x^2} are their Maclaurin series,
 // truncated below 1e-17; elsewhere the library's erfc and exp.  D is double (or a counting type).
 template <class D>
-__host__ __device__ __forceinline__ void normal_split(D U, D var, D& pp, D& pm, D& tail) {
+__host__ __device__ __forceinline__ void normal_split(D U, D var, D& pp, D& pm, D& tail, const SplitSeries& ss) {
   const D isv = rsqrt64(var);
   const D x = U * isv * D(0.70710678118654752440);
   const D y = -(x * x);
   D g;
   if (fabs(x) < D(0.5)) {
-    // erf(x) = (2/sqrt(pi)) x sum_n y^n / (n! (2n+1)), n = 0..11
-    D s = D(1.0 / 918086400.0);
-    s = s * y + D(1.0 / 76204800.0);
-    s = s * y + D(1.0 / 6894720.0);
-    s = s * y + D(1.0 / 685440.0);
-    s = s * y + D(1.0 / 75600.0);
-    s = s * y + D(1.0 / 9360.0);
-    s = s * y + D(1.0 / 1320.0);
-    s = s * y + D(1.0 / 216.0);
-    s = s * y + D(1.0 / 42.0);
-    s = s * y + D(1.0 / 10.0);
-    s = s * y + D(1.0 / 3.0);
-    s = s * y + D(1.0);
+    D s = D(ss.erf_c[0]);
+#pragma unroll
+    for (int k = 1; k < 12; ++k) s = s * y + D(ss.erf_c[k]);
     const D he = D(0.56418958354775628695) * x * s;  // erf(x) / 2
     pp = D(0.5) + he;
     pm = D(0.5) - he;
-    // e^y = sum_n y^n / n!, n = 0..12
-    g = D(1.0 / 479001600.0);
-    g = g * y + D(1.0 / 39916800.0);
-    g = g * y + D(1.0 / 3628800.0);
-    g = g * y + D(1.0 / 362880.0);
-    g = g * y + D(1.0 / 40320.0);
-    g = g * y + D(1.0 / 5040.0);
-    g = g * y + D(1.0 / 720.0);
-    g = g * y + D(1.0 / 120.0);
-    g = g * y + D(1.0 / 24.0);
-    g = g * y + D(1.0 / 6.0);
-    g = g * y + D(0.5);
-    g = g * y + D(1.0);
-    g = g * y + D(1.0);
+    g = D(ss.exp_c[0]);
+#pragma unroll
+    for (int k = 1; k < 13; ++k) g = g * y + D(ss.exp_c[k]);
   } else {
     const D c = D(0.5) * derfc(fabs(x));
     if (x > D(0)) {

@@ -116,9 +116,9 @@ inline Fl rcp64(Fl x) {
 // steps, written out so that their operations are counted
 inline Fl rsqrt64(Fl x) {
   Fl y = un('q', x, 1.0 / std::sqrt(x.v()));
-  const Fl hx = Fl(0.5) * x;
-  y = y * fma(-(hx * y), y, Fl(1.5));
-  y = y * fma(-(hx * y), y, Fl(1.5));
+  const Fl mhx = Fl(-0.5) * x;
+  y = fma(y, fma(mhx * y, y, Fl(0.5)), y);
+  y = fma(y, fma(mhx * y, y, Fl(0.5)), y);
   return y;
 }
 inline Fl dfma(Fl a, Fl b, Fl c) { return fma(a, b, c); }
@@ -146,7 +146,7 @@ static void reset() {
 
 int main() {
   // --- k_flux5 per face: the 10 (variable, side) polynomials at the 4 Gauss points, then per point
-  //     the flux, the 4-lane Gauss average and the 0.25 scaling of its 30 outputs
+  //     the flux (its outputs weighted by 1/4) and the 4-lane Gauss sum of its 30 outputs
   const FluxParams fp = make_flux_params(1.4, 6.25e-4, 71.43, 0.72, 0.05, 10.0);
   double WL[5] = {1.0, 0.3, 0.1, -0.2, 180.0}, WR[5] = {1.01, 0.31, 0.09, -0.21, 180.2};
   Fl DL[15], DR[15], VL[5], VR[5], out[25], Fn[5];
@@ -168,10 +168,10 @@ int main() {
     VL[v] = leaf(1e-3 * (v + 1));
     VR[v] = leaf(-1e-3 * (v + 2));
   }
-  gks_flux<Fl, true, Fl>(fp, 1e-3, WL, VL, DL, WR, VR, DR, Fn, out);
+  gks_flux<Fl, true, Fl>(fp, 1e-3, WL, VL, DL, WR, VR, DR, Fn, out, NoPark(), 0.25);
   const long long flux_flops = fc::n_flop;
   const long long flux_trans = fc::n_trans;
-  const long long reduce_flops = 30 * 3;  // two lane sums and the 1/4 scaling per output
+  const long long reduce_flops = 30 * 2;  // two lane sums per output
 
   // --- one cell of k_coef: stencil data (h dQ products counted by the type, 18 FP64 differences by
   //     hand), a = R d, and optionally GENO

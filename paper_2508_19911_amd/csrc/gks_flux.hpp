@@ -187,6 +187,7 @@ struct FluxParams {
   double tau_eps, tau_c;
   double ik3;        // 1 / (Kdof + 3)
   double itref;      // 1 / tref (0 when tref <= 0)
+  SplitSeries split; // series coefficients of the FP64 split at u = 0
 };
 
 inline FluxParams make_flux_params(double gamma, double mu0, double tref, double prandtl,
@@ -201,6 +202,7 @@ inline FluxParams make_flux_params(double gamma, double mu0, double tref, double
   f.tau_c = tau_c;
   f.ik3 = 1.0 / (f.Kdof + 3.0);
   f.itref = tref > 0.0 ? 1.0 / tref : 0.0;
+  f.split = make_split_series();
   return f;
 }
 
@@ -238,7 +240,9 @@ __host__ __device__ __forceinline__ T bulk(D x) {
 // face-frame axis d.  Outputs: Fn[5] = F^n (FP64); out[0..4] = F_t; with IFACE also
 // out[5..9] = Q^l_n - Q0L, out[10..14] = Q^l_t, out[15..19] = Q^r_n - Q0R, out[20..24] = Q^r_t
 // (interface values relative to the own cell's average, which cancels in the closed surface sum of
-// the cell's gradient).  D is double (a counting type in the flop counter).
+// the cell's gradient).  Every output is multiplied by qw (a Gauss weight, so that a sum over the
+// points of a face needs no scaling; a power of two leaves the results bit for bit those of scaling
+// the sum).  D is double (a counting type in the flop counter).
 //
 // Each Maxwellian (the two sides, then g0) is handled in its own tangentially co-moving frame, where
 // the moment products are sparse; the results are shifted back to the lab before they are summed.
@@ -248,7 +252,7 @@ template <class T, bool IFACE, class D = double, class Park = NoPark>
 __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt, const double* Q0L,
                                                   const T* VL, const T* DL, const double* Q0R,
                                                   const T* VR, const T* DR, D* Fn, T* out,
-                                                  Park park = Park()) {
+                                                  Park park = Park(), double qw = 1.0) {
   const T K = T(P.Kdof);
   const T ik3 = T(P.ik3);
   const D gm1 = D(P.gamma - 1.0);
@@ -279,7 +283,7 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
     pr[s].var = bulk<T>(var);
     pr[s].lam = T(0.5) * drcp(pr[s].var);
     D pp, pm, tail;
-    normal_split(U, var, pp, pm, tail);
+    normal_split(U, var, pp, pm, tail, P.split);
     const D u0 = s == 0 ? pp : pm;
     const D u1 = s == 0 ? U * u0 + tail : U * u0 - tail;
     const D u2 = U * u1 + var * u0;
@@ -324,15 +328,16 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
   if constexpr (IFACE) {
     w = dexp(-drcp(T(P.tau_c) * jump));
     w1 = T(1) - w;
+    const T w1q = T(qw) * w1, wq = T(qw) * w;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      oL[v] = w1 * bulk<T>(W0[v] - data<D>(Q0L[v])) + w * VL[v];
-      oR[v] = w1 * bulk<T>(W0[v] - data<D>(Q0R[v])) + w * VR[v];
+      oL[v] = w1q * bulk<T>(W0[v] - data<D>(Q0L[v])) + wq * VL[v];
+      oR[v] = w1q * bulk<T>(W0[v] - data<D>(Q0R[v])) + wq * VR[v];
     }
   }
   D G0p[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) G0p[v] = G0[v];
+  for (int v = 0; v < 5; ++v) G0p[v] = D(qw) * G0[v];
   park.save(G0p, dS, oL, oR);
 
   // lab sums over the two sides, each piece density-weighted on its half space:
@@ -486,6 +491,11 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
   ct[2] = T(1) - T(4) * rom * rom;
   ct[4] = -ct[1];
   ct[5] = T(4) * rom * rom;
+#pragma unroll
+  for (int k = 1; k < 6; ++k) cn[k] = T(qw) * cn[k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    if (k != 3) ct[k] = T(qw) * ct[k];
 
   park.load(G0p, dS, oL, oR);
   // F^n = (1 - cn3) G0 + cn3 SP0 + the slope and time-derivative products = G0 (FP64) + dF (T);
@@ -518,9 +528,9 @@ __host__ __device__ __forceinline__ void gks_flux(const FluxParams& P, double dt
     for (int v = 0; v < 5; ++v) {
       const T Qt = ctq * G[4][v] + ct[4] * SP[4][v] + ct[5] * SP[5][v];
       out[5 + v] = oL[v] + w1 * qs[v];
-      out[10 + v] = w1 * Qt + w * eul[0][v];
+      out[10 + v] = w1 * Qt + T(qw) * w * eul[0][v];
       out[15 + v] = oR[v] + w1 * qs[v];
-      out[20 + v] = w1 * Qt + w * eul[1][v];
+      out[20 + v] = w1 * Qt + T(qw) * w * eul[1][v];
     }
   }
 }

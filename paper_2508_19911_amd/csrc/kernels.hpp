@@ -388,13 +388,13 @@ __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 1 : 3) void k_flux5(Grid
   }
   double Fn[5];
   T out[25];
+  // each point's outputs come weighted by 1/4; the 2x2 Gauss average is their sum over the face's lanes
   gks_flux<T, true>(fp, dt, QL0, VL, DL, QR0, VR, DR, Fn, out,
-                    LdsPark<T>{reinterpret_cast<char*>(&sh.D[0][0][0][0]), (int)threadIdx.x});
-  // 2x2 Gauss average over the four lanes of the face
+                    LdsPark<T>{reinterpret_cast<char*>(&sh.D[0][0][0][0]), (int)threadIdx.x}, 0.25);
 #pragma unroll
-  for (int n = 0; n < 5; ++n) Fn[n] = 0.25 * quad_sum(Fn[n]);
+  for (int n = 0; n < 5; ++n) Fn[n] = quad_sum(Fn[n]);
 #pragma unroll
-  for (int n = 0; n < 25; ++n) out[n] = T(0.25) * quad_sum(out[n]);
+  for (int n = 0; n < 25; ++n) out[n] = quad_sum(out[n]);
   if (active) {
     // every lane of a face holds the face's sums; all four store them (the four lanes of a face
     // write the same bytes, which the store merges), so no lane branches on its output.  F^n goes to
