@@ -271,7 +271,6 @@ constexpr int FLUX_BLK = 4 * FLUX_FACES;
 
 template <class T>
 struct FluxShared {
-  double Q0[FLUX_FACES][10];     // [face][side * 5 + face-frame variable]: the side's cell average
   T V[FLUX_FACES][4][10];        // [face][point][side * 5 + variable]: point value minus the average
   T D[FLUX_FACES][4][10][3];     // face-frame derivatives, physical units
 };
@@ -363,8 +362,6 @@ __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 1 : 3) void k_flux5(Grid
       }
       T val[4], der[4][3];
       eval_face<FP>(a, side ? T(-1) : T(1), val, der);
-      const double q0 = ld(Q + vg * N, (uint32_t)src);
-      sh.Q0[fl][vs] = q0;
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         sh.V[fl][p][vs] = val[p];
@@ -380,8 +377,11 @@ __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 1 : 3) void k_flux5(Grid
   for (int vf = 0; vf < 5; ++vf) {
     VL[vf] = sh.V[fl][kgp][vf];
     VR[vf] = sh.V[fl][kgp][5 + vf];
-    QL0[vf] = sh.Q0[fl][vf];
-    QR0[vf] = sh.Q0[fl][5 + vf];
+    // the two cells' FP64 averages straight from memory (the four lanes of a face read the same
+    // values); handed over through LDS by the polynomial phase, they cost more
+    const int vg = (vf >= 1 && vf <= 3) ? 1 + (DIR + vf - 1) % 3 : vf;
+    QL0[vf] = ld(Q + vg * N, (uint32_t)left);
+    QR0[vf] = ld(Q + vg * N, (uint32_t)cell);
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd) {
       DL[dd * 5 + vf] = sh.D[fl][kgp][vf][dd];
