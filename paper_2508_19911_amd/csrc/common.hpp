@@ -105,15 +105,27 @@ inline SplitSeries make_split_series() {
 // The split at u = 0 of a Maxwellian's normal velocity (mean U, variance var = p/rho), in FP64:
 // pp = P(u > 0) = erfc(-x)/2 and pm = P(u < 0) = erfc(x)/2 with x = U/sqrt(2 var), and
 // tail = e^{-x^2} sqrt(var/(2 pi)), so that <u>_{u>0} = U pp + tail and <u>_{u<0} = U pm - tail.
-// For |x| < 1/2 (every point of a low-Mach flow) erf(x) and e^{-x^2} are their Maclaurin series,
-// truncated below 1e-17; elsewhere the library's erfc and exp.  D is double (or a counting type).
+// For |x| < 1/2 erf(x) and e^{-x^2} are their Maclaurin series, truncated below 1e-17 (for |x| < 1/8,
+// where every point of a low-Mach flow lies, the first 7 and 8 terms reach that); elsewhere the
+// library's erfc and exp.  D is double (or a counting type).
 template <class D>
 __host__ __device__ __forceinline__ void normal_split(D U, D var, D& pp, D& pm, D& tail, const SplitSeries& ss) {
   const D isv = rsqrt64(var);
   const D x = U * isv * D(0.70710678118654752440);
   const D y = -(x * x);
   D g;
-  if (fabs(x) < D(0.5)) {
+  if (fabs(x) < D(0.125)) {
+    // omitted terms: (1/64)^7 / (7! 15) < 3e-18 and (1/64)^8 / 8! < 1e-19
+    D s = D(ss.erf_c[5]);
+#pragma unroll
+    for (int k = 6; k < 12; ++k) s = s * y + D(ss.erf_c[k]);
+    const D he = D(0.56418958354775628695) * x * s;  // erf(x) / 2
+    pp = D(0.5) + he;
+    pm = D(0.5) - he;
+    g = D(ss.exp_c[5]);
+#pragma unroll
+    for (int k = 6; k < 13; ++k) g = g * y + D(ss.exp_c[k]);
+  } else if (fabs(x) < D(0.5)) {
     D s = D(ss.erf_c[0]);
 #pragma unroll
     for (int k = 1; k < 12; ++k) s = s * y + D(ss.erf_c[k]);

@@ -42,6 +42,12 @@ void host_point_flux(int precision, double gamma, double mu0, double tref, doubl
   }
 }
 
+// The FP64 split of a Maxwellian's normal velocity at u = 0 (mean U, variance var): out = {pp, pm, tail}.
+void host_normal_split(double U, double var, double* out) {
+  const SplitSeries ss = make_split_series();
+  normal_split(U, var, out[0], out[1], out[2], ss);
+}
+
 // The 34 coefficients a of one variable evaluated at the 4 Gauss points of the face of axis e on the
 // + side (sn = +1) or the - side (sn = -1) by the parity-class routine of the flux kernel:
 // val[4], der[4][3] (normalised derivatives).

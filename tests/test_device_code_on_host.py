@@ -39,6 +39,7 @@ def lib():
     D, P = ctypes.c_double, ctypes.c_void_p
     L.host_point_flux.argtypes = [ctypes.c_int] + [D] * 7 + [P, P, P]
     L.host_eval_face.argtypes = [ctypes.c_int, D, P, P, P]
+    L.host_normal_split.argtypes = [D, D, P]
     return L
 
 
@@ -128,3 +129,28 @@ def test_fp32_form_keeps_the_pressure_scale_in_fp64(lib):
     # F^n and the two sides' interface values (absolute; |F| and |Q| up to ~250)
     assert err[0:5].max() <= 1e-9, err[0:5]
     assert err[10:15].max() <= 1e-9 and err[20:25].max() <= 1e-9, (err[10:15], err[20:25])
+
+
+def test_normal_split_series_and_library_branches(lib):
+    """The FP64 split at u = 0 (probabilities of u > 0 and u < 0, and the half-range tail) on both sides
+    of the two series branches (|x| = 1/8 and 1/2, x = U / sqrt(2 var)) and on the library branch,
+    against erfc and exp evaluated by SciPy: the short series (7 and 8 terms below |x| = 1/8) and the
+    long one (12 and 13 terms) must both be exact to FP64 rounding, and pp + pm = 1."""
+    from scipy.special import erfc
+
+    var = 1.7
+    xs = np.concatenate([np.linspace(-1.3, 1.3, 261), [0.0, 0.1249999, 0.1250001, -0.1250001, 0.4999999, 0.5000001,
+                                                         -0.4999999, 1e-9, -3e-5, 0.07, 0.3]])
+    out = np.zeros(3)
+    for x in xs:
+        U = x * np.sqrt(2.0 * var)
+        lib.host_normal_split(U, var, _p(out))
+        pp, pm = 0.5 * erfc(-x), 0.5 * erfc(x)
+        tail = np.exp(-x * x) * np.sqrt(var / (2.0 * np.pi))
+        # a few ulp: x itself carries the rounding of U / sqrt(2 var); the library branch's erfc and
+        # SciPy's differ by up to a few ulp where erfc is steep
+        bar = 6e-16 if abs(x) < 0.5 else 3e-15
+        assert abs(out[0] - pp) <= bar * pp, (x, out[0], pp)
+        assert abs(out[1] - pm) <= bar * pm, (x, out[1], pm)
+        assert abs(out[2] - tail) <= bar * tail, (x, out[2], tail)
+        assert abs(out[0] + out[1] - 1.0) <= 4e-16
