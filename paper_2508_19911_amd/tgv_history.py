@@ -98,7 +98,10 @@ def main():
         ("cgks5_fp64_plain", base.with_(recon=cgks.RECON_NONLINEAR), cgks.PREC_FP64, None),
         ("gks2_fp64_linear", base.with_(scheme=cgks.SCHEME_GKS2, recon=cgks.RECON_LINEAR), cgks.PREC_FP64, None),
     ]
-    out = {"grid": n, "cfl": base.cfl, "dt_out": args.dt_out, "variants": {}}
+    from .equal_l2 import kernel_digest
+
+    out = {"grid": n, "cfl": base.cfl, "dt_out": args.dt_out, "kernel_sources_sha256": kernel_digest(),
+           "variants": {}}
     fields = {}
     t_end = tc if args.reference_only else args.t_end
     for name, case, prec, indicator in variants:
