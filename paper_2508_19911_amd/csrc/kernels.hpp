@@ -344,24 +344,56 @@ __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 1 : 3) void k_flux5(Grid
   cell_ijk(g, cell, i, j, k);
   const int left = neighbour_m<DIR>(g, cell, i, j, k);
   const long long N = g.N;
+  // the two cells' FP64 averages for phase 2, issued now so that their latency passes under phase 1
+  double QL0[5], QR0[5];
+#pragma unroll
+  for (int vf = 0; vf < 5; ++vf) {
+    const int vg = (vf >= 1 && vf <= 3) ? 1 + (DIR + vf - 1) % 3 : vf;
+    QL0[vf] = ld(Q + vg * N, (uint32_t)left);
+    QR0[vf] = ld(Q + vg * N, (uint32_t)cell);
+  }
+  // Phase 1.  Round r gives this lane the polynomial (side, face-frame variable) vs = 4 r + kgp; the
+  // last round has 2 of them per face.  Every round's chunk loads are written ahead of the
+  // evaluations, so that a round's loads are in flight while the round before is evaluated (the
+  // compiler issues the last round's once the first round's registers are free).  The padding of a
+  // partial last chunk is not loaded: a register whose unused part is reused by other values must
+  // wait for its load, and that wait would take in every load issued before it.
+  constexpr int TAIL = tab::NB - (CB::NCH - 1) * CB::PER;  // valid coefficients of the last chunk
+  static_assert(TAIL == CB::PER || TAIL == 2, "last chunk: whole, or two coefficients");
+  using V2 = T __attribute__((ext_vector_type(2)));
+  auto chunks = [&](int r, T* x) {
+    // the two lanes of a face with no polynomial in the last round load their neighbours' (and drop
+    // it), so that every round's loads are unconditional and their waits exact
+    const int vs = 4 * r + kgp < 10 ? 4 * r + kgp : 4 * r + kgp - 2;
+    const int side = vs >= 5 ? 1 : 0;  // 0: the low cell (its + face), 1: this cell (its - face)
+    const int vf = vs - 5 * side;
+    const int vg = (vf >= 1 && vf <= 3) ? 1 + (DIR + vf - 1) % 3 : vf;
+    const T* cb = C + CB::base(side ? cell : left, vg);
+#pragma unroll
+    for (int c = 0; c < CB::NCH; ++c) {
+      if (c < CB::NCH - 1 || TAIL == CB::PER) {
+        const V v = *reinterpret_cast<const V*>(cb + c * CB::CHUNK_STRIDE);
+#pragma unroll
+        for (int e = 0; e < CB::PER; ++e) x[c * CB::PER + e] = v[e];
+      } else {
+        const V2 v = *reinterpret_cast<const V2*>(cb + c * CB::CHUNK_STRIDE);
+        x[c * CB::PER] = v[0];
+        x[c * CB::PER + 1] = v[1];
+      }
+    }
+  };
+  T xs[3][tab::NB + 2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) chunks(r, xs[r]);
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    const int vs = 4 * r + kgp;  // side * 5 + face-frame variable
+    // every lane evaluates (the wave issues the instructions either way); the two lanes of a face
+    // with no polynomial in the last round do not store theirs
+    const int vs = 4 * r + kgp;
+    const int side = vs >= 5 ? 1 : 0;
+    T val[4], der[4][3];
+    eval_face<FP>(xs[r], side ? T(-1) : T(1), val, der);
     if (r < 2 || vs < 10) {
-      const int side = vs >= 5 ? 1 : 0;  // 0: the low cell (its + face), 1: this cell (its - face)
-      const int vf = vs - 5 * side;
-      const int vg = (vf >= 1 && vf <= 3) ? 1 + (DIR + vf - 1) % 3 : vf;
-      const int src = side ? cell : left;
-      const T* cb = C + CB::base(src, vg);
-      T a[CB::NBP];
-#pragma unroll
-      for (int c = 0; c < CB::NCH; ++c) {
-        const V x = *reinterpret_cast<const V*>(cb + c * CB::CHUNK_STRIDE);
-#pragma unroll
-        for (int e = 0; e < CB::PER; ++e) a[c * CB::PER + e] = x[e];
-      }
-      T val[4], der[4][3];
-      eval_face<FP>(a, side ? T(-1) : T(1), val, der);
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
         sh.V[fl][p][vs] = val[p];
@@ -371,17 +403,11 @@ __global__ __launch_bounds__(FLUX_BLK, sizeof(T) == 8 ? 1 : 3) void k_flux5(Grid
     }
   }
   __syncthreads();
-  double QL0[5], QR0[5];
   T VL[5], VR[5], DL[15], DR[15];
 #pragma unroll
   for (int vf = 0; vf < 5; ++vf) {
     VL[vf] = sh.V[fl][kgp][vf];
     VR[vf] = sh.V[fl][kgp][5 + vf];
-    // the two cells' FP64 averages straight from memory (the four lanes of a face read the same
-    // values); handed over through LDS by the polynomial phase, they cost more
-    const int vg = (vf >= 1 && vf <= 3) ? 1 + (DIR + vf - 1) % 3 : vf;
-    QL0[vf] = ld(Q + vg * N, (uint32_t)left);
-    QR0[vf] = ld(Q + vg * N, (uint32_t)cell);
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd) {
       DL[dd * 5 + vf] = sh.D[fl][kgp][vf][dd];
