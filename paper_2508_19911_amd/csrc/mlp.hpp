@@ -297,18 +297,40 @@ __global__ __launch_bounds__(256) void k_infer(Grid g, const double* __restrict_
   constexpr int OWS2 = 32 * XS, OWS3 = OWS2 + 32 * HS, NWS = OWS3 + 32 * HS;
   __shared__ alignas(16) uint16_t wsh[NWS];
   __shared__ float bsh[3 * 32 + 32 + 1];
-  for (int n = threadIdx.x; n < 32 * 64; n += 256) wsh[(n >> 6) * XS + (n & 63)] = f2bf(params[OW1 + n]);
-  for (int n = threadIdx.x; n < 32 * 32; n += 256) {
-    wsh[OWS2 + (n >> 5) * HS + (n & 31)] = f2bf(params[OW2 + n]);
-    wsh[OWS3 + (n >> 5) * HS + (n & 31)] = f2bf(params[OW3 + n]);
+  {
+    // every load of the staging first (16-byte loads: W1 is 512 of them, W2 and W3 256 each, all
+    // 16-byte aligned), then the conversions and LDS stores; a loop that stored each weight before
+    // loading the next waited for every load in turn
+    const int t = (int)threadIdx.x & 255;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4* p4 = reinterpret_cast<const f4*>(params);
+    static_assert(OW1 % 4 == 0 && OW2 % 4 == 0 && OW3 % 4 == 0, "16-byte weight rows");
+    const f4 a0 = p4[OW1 / 4 + t], a1 = p4[OW1 / 4 + 256 + t], b = p4[OW2 / 4 + t], c = p4[OW3 / 4 + t];
+    float bias[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (t < 32) {
+      bias[0] = params[OB1 + t];
+      bias[1] = params[OB2 + t];
+      bias[2] = params[OB3 + t];
+      bias[3] = params[OW4 + t];
+    }
+    const float b4 = t == 0 ? params[OB4] : 0.0f;
+    auto put4 = [&](int off, const f4& x) {
+      *reinterpret_cast<bf16x4*>(wsh + off) = bf16x4{(short)f2bf(x[0]), (short)f2bf(x[1]), (short)f2bf(x[2]), (short)f2bf(x[3])};
+    };
+    // element n = 4 (t or 256 + t) of W1 sits in row n / 64 at column n % 64; of W2, W3 row n / 32
+    put4(((4 * t) >> 6) * XS + ((4 * t) & 63), a0);
+    put4(((4 * (256 + t)) >> 6) * XS + ((4 * (256 + t)) & 63), a1);
+    put4(OWS2 + ((4 * t) >> 5) * HS + ((4 * t) & 31), b);
+    put4(OWS3 + ((4 * t) >> 5) * HS + ((4 * t) & 31), c);
+    if (t < 32) {
+      bsh[t] = bias[0];
+      bsh[32 + t] = bias[1];
+      bsh[64 + t] = bias[2];
+      bsh[96 + t] = bias[3];
+    }
+    if (t == 0) bsh[128] = b4;
   }
-  for (int n = threadIdx.x; n < 32; n += 256) {
-    bsh[n] = params[OB1 + n];
-    bsh[32 + n] = params[OB2 + n];
-    bsh[64 + n] = params[OB3 + n];
-    bsh[96 + n] = params[OW4 + n];
-  }
-  if (threadIdx.x == 0) bsh[128] = params[OB4];
+  static_assert(XS % 4 == 0 && HS % 4 == 0 && OWS2 % 4 == 0 && OWS3 % 4 == 0, "8-byte aligned weight rows");
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int base = blockIdx.x * 256 + w * 64;
