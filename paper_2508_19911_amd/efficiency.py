@@ -102,8 +102,11 @@ def main():
     cgks.load()
     c5, c2, paper = flow_cases(args.flow)
     quad = not args.one_point
+    from .equal_l2 import kernel_digest
+
     out = {"flow": args.flow, "t_end": args.t_end, "cfl": c5.cfl, "paper_table": paper,
-           "diagnostics": "quadrature" if quad else "one-point", "runs": {}}
+           "diagnostics": "quadrature" if quad else "one-point", "kernel_sources_sha256": kernel_digest(),
+           "runs": {}}
     out["runs"]["cgks5_fp64"] = run(cgks, c5, cgks.PREC_FP64, args.t_end, args.dt_out, "cgks5_fp64", quad=quad)
     print(json.dumps({k: v for k, v in out["runs"]["cgks5_fp64"].items() if k != "history"}), flush=True)
     if args.fp32:
